@@ -1,0 +1,197 @@
+/*
+ * lbpf.h -- C ABI of liblbpf.so: depth-fused LBP face features and linear-SVM
+ * scoring on AMD Instinct MI355X (gfx950), after Naik & Rathna, "Robust real
+ * time face recognition and tracking on GPU using fusion of RGB and depth
+ * image" (arXiv 1504.01883).
+ *
+ * The library computes, for face boxes given in co-registered grey (u8) and
+ * depth (u16, millimetres, 0 = invalid) planes:
+ *   1. the lower median m of the crop's non-zero depth (the depth region of
+ *      interest that the paper's fusion relies on, abstract and Sec. 1);
+ *   2. for every interior pixel whose depth d satisfies d != 0 and
+ *      |d - m| < depth_window_mm, the 3x3 LBP code of the grey and of the
+ *      depth plane (Sec. 2.4, Eq. 2, Fig. 7; neighbour p gets weight 2^p,
+ *      bit set when the neighbour is >= the centre; p0 is the top-left
+ *      neighbour and p runs clockwise);
+ *   3. the uniform-59 bin of each code (58 uniform patterns in increasing
+ *      order, then one bin for all others) or the raw 256-bin code;
+ *   4. regional histograms over a grid_x x grid_y grid whose band r covers
+ *      [floor(r*n/g), floor((r+1)*n/g)) of a side of length n (Sec. 2.4,
+ *      Eq. 3), concatenated as [channel][ry][rx][bin], grey first;
+ *   5. the L1-normalised feature x = count / T with T = channels * n_in,
+ *      each element the correctly rounded single-precision quotient (0 when
+ *      T = 0);
+ *   6. SVM decision values S = X W^T + b for every enrolled identity and the
+ *      best identity per crop (Sec. 2.5: one hyperplane per person; ties go
+ *      to the lowest identity index).
+ *
+ * Conventions for every call:
+ *   - Pointers documented as DEVICE point to GPU memory the caller allocated
+ *     (hipMalloc or a torch CUDA tensor); HOST pointers are ordinary memory.
+ *     The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls taking a stream are asynchronous: they return once the work is
+ *     queued. Faults during execution surface at the caller's next
+ *     synchronisation of that stream.
+ *   - Every argument check happens before anything is queued: on an error
+ *     return nothing was written and no work was queued.
+ *   - lbpf_features / lbpf_features_batch / lbpf_score never allocate device
+ *     memory; all scratch is owned by the context and sized at creation.
+ *   - A context is used by one host thread at a time; several contexts may
+ *     coexist. Work queued on different streams through the same context may
+ *     overlap only for lbpf_features_batch and lbpf_score (lbpf_features
+ *     stages box tables through a small ring of buffers and waits for the
+ *     oldest slot before reusing it).
+ */
+#ifndef LBPF_H
+#define LBPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbpf_status {
+    LBPF_OK = 0,
+    LBPF_E_INVALID = -1,     /* bad argument: NULL pointer, box outside its image, side < 3 ... */
+    LBPF_E_BUDGET = -2,      /* request larger than the context's fixed capacity or budget */
+    LBPF_E_HIP = -3,         /* a HIP runtime call failed; lbpf_last_error() has the detail */
+    LBPF_E_UNSUPPORTED = -4  /* valid request this build does not implement */
+} lbpf_status;
+
+typedef enum lbpf_precision {
+    LBPF_FP32 = 0,       /* FP32 operands, FP32 MFMA accumulation */
+    LBPF_BF16 = 1,       /* BF16 operands (round to nearest even), FP32 accumulation */
+    LBPF_FP16 = 2,       /* FP16 operands with per-row power-of-two scales */
+    LBPF_FP8_E4M3 = 3    /* OCP FP8 e4m3 operands with per-row amax/448 scales */
+} lbpf_precision;
+
+enum { LBPF_MAP_U59 = 0, LBPF_MAP_FULL256 = 1 };
+enum { LBPF_MOD_BOTH = 0, LBPF_MOD_GREY = 1, LBPF_MOD_DEPTH = 2 };
+
+/* One co-registered grey + depth image. grey and depth are DEVICE pointers to
+ * row-major planes; pitches are in elements (bytes for grey, u16 for depth).
+ * grey may be NULL only when the context's modality is LBPF_MOD_DEPTH. */
+typedef struct lbpf_image {
+    const uint8_t *grey;
+    const uint16_t *depth;
+    int32_t width, height, grey_pitch, depth_pitch;
+} lbpf_image;
+
+/* A face box in image `image`: the crop is columns [x, x+w) and rows [y, y+h)
+ * of both planes (the paper maps the detected face to a rectangle of the
+ * depth frame, Sec. 2.1). Requires 3 <= w, h <= LBPF_MAX_SIDE and the box
+ * inside its image. */
+typedef struct lbpf_box {
+    int32_t image, x, y, w, h;
+} lbpf_box;
+
+#define LBPF_MAX_SIDE 1024
+
+/* Feature configuration. grid_x * grid_y <= 64 and each >= 1; mapping is
+ * LBPF_MAP_U59 (59 bins) or LBPF_MAP_FULL256 (256 bins, the paper's "0 to
+ * 255" histogram, Sec. 3); depth_window_mm > 0 enables the depth mask with
+ * that half-width, <= 0 counts every interior pixel; modality selects the
+ * channels (Table 1 compares grey-only and depth-only inputs). */
+typedef struct lbpf_feature_cfg {
+    int32_t grid_x, grid_y;
+    int32_t mapping;
+    int32_t depth_window_mm;
+    int32_t modality;
+} lbpf_feature_cfg;
+
+typedef struct lbpf_ctx lbpf_ctx;         /* workspace, pinned staging ring, lookup tables */
+typedef struct lbpf_weights lbpf_weights; /* device-resident W, b and any quantised copy */
+typedef struct lbpf_batch lbpf_batch;     /* device-resident, validated box table */
+
+/* Library version string, e.g. "lbpf 0.1.0 gfx950". Never NULL. */
+const char *lbpf_version(void);
+
+/* Create a context on the current HIP device. cfg NULL selects the default
+ * {8, 8, LBPF_MAP_U59, 150, LBPF_MOD_BOTH}. hbm_budget_bytes bounds the
+ * device memory the context and its batches may hold (0 = no bound).
+ * Allocates the context's fixed workspace (box staging for up to
+ * LBPF_MAX_BOXES_PER_CALL boxes and the scoring scratch).
+ * Returns LBPF_E_INVALID for a bad cfg, LBPF_E_BUDGET when the workspace alone
+ * exceeds the budget, LBPF_E_HIP when an allocation fails. */
+#define LBPF_MAX_BOXES_PER_CALL 65536
+lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_budget_bytes);
+
+/* Release the context and its workspace (synchronises the device first).
+ * NULL is allowed. Batches and weights created from it must be destroyed
+ * before it. */
+void lbpf_destroy(lbpf_ctx *ctx);
+
+/* Feature dimension D = channels * grid_x * grid_y * bins (7552 for the
+ * default configuration), or -1 for a NULL context. */
+int32_t lbpf_feature_dim(const lbpf_ctx *ctx);
+
+/* Features of n_boxes boxes. images (n_images entries) and boxes (n_boxes
+ * entries) are HOST arrays; the planes they point to are DEVICE memory.
+ * hist: DEVICE [n_boxes][D] FP32, L1-normalised (steps 1-5 above).
+ * counts_opt: DEVICE [n_boxes][D] u32 raw histogram counts, or NULL.
+ * The box table is validated on the host, copied through pinned memory and
+ * the kernels are queued on `stream`. n_boxes = 0 is a no-op.
+ * Errors: LBPF_E_INVALID (NULL pointers, a box outside its image or with a
+ * side < 3 or > LBPF_MAX_SIDE, a NULL grey plane when grey is used),
+ * LBPF_E_BUDGET (n_boxes > LBPF_MAX_BOXES_PER_CALL), LBPF_E_HIP. */
+lbpf_status lbpf_features(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                          const lbpf_box *boxes, int32_t n_boxes, float *hist,
+                          uint32_t *counts_opt, void *stream);
+
+/* Validate a box table once and keep it in device memory, for repeated
+ * launches over inputs that stay resident (benchmarks, hipGraph capture).
+ * HOST arrays in, synchronous. The batch records the planes' DEVICE pointers:
+ * the caller keeps them alive while the batch is used. Same errors as
+ * lbpf_features, plus LBPF_E_BUDGET when the context's budget is exceeded. */
+lbpf_status lbpf_batch_create(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                              const lbpf_box *boxes, int32_t n_boxes, lbpf_batch **out);
+void lbpf_batch_destroy(lbpf_batch *batch);
+int32_t lbpf_batch_size(const lbpf_batch *batch);
+
+/* Features of a prepared batch: same outputs as lbpf_features, no host
+ * staging and no allocation. hist and counts_opt are DEVICE [n][D]. */
+lbpf_status lbpf_features_batch(lbpf_ctx *ctx, const lbpf_batch *batch, float *hist,
+                                uint32_t *counts_opt, void *stream);
+
+/* Enrol K identities: W DEVICE [K][D] FP32 row-major, b DEVICE [K] FP32.
+ * The library copies them (and, for BF16/FP16/FP8, quantises them) into a
+ * weights object it owns; the caller's buffers may be freed once `stream`
+ * has finished. Synchronous with respect to the host. Errors: LBPF_E_INVALID
+ * (K < 1, NULL), LBPF_E_UNSUPPORTED (precision not built), LBPF_E_BUDGET,
+ * LBPF_E_HIP. */
+lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, int32_t K,
+                                lbpf_precision precision, lbpf_weights **out, void *stream);
+void lbpf_weights_destroy(lbpf_weights *weights);
+int32_t lbpf_weights_count(const lbpf_weights *weights);
+
+/* Score N feature rows against every enrolled identity (step 6).
+ * hist: DEVICE [N][D] FP32. scores_opt: DEVICE [N][K] FP32 or NULL.
+ * argmax_opt: DEVICE [N] int32 or NULL (not both NULL). N = 0 is a no-op.
+ * In FP32 the scores are accumulated in FP32 by MFMA; in the reduced
+ * precisions the operands are converted as documented for lbpf_precision and
+ * the products accumulated in FP32. Errors: LBPF_E_INVALID, LBPF_E_HIP. */
+lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_weights *weights,
+                       float *scores_opt, int32_t *argmax_opt, void *stream);
+
+/* Test hook: per-pixel codes and mask of ONE box, for bit-exact checks.
+ * image/box are HOST structs; grey_codes, depth_codes, mask are DEVICE
+ * [box->h][box->w] u8 arrays. Interior pixels receive their grey code, depth
+ * code and mask bit (1 = counted); border entries are written as 0. */
+lbpf_status lbpf_debug_codes(lbpf_ctx *ctx, const lbpf_image *image, const lbpf_box *box,
+                             uint8_t *grey_codes, uint8_t *depth_codes, uint8_t *mask,
+                             void *stream);
+
+/* Human-readable name of a status code. Never NULL. */
+const char *lbpf_status_string(lbpf_status status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *lbpf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBPF_H */

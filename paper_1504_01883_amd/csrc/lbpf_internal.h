@@ -1,0 +1,53 @@
+// Internal declarations shared by the HIP sources of liblbpf.so.
+// Nothing here is part of the public ABI (include/lbpf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lbpf.h"
+
+namespace lbpf {
+
+// One face crop, resolved on the host from (image, box): plane pointers at
+// the crop origin, pitches in elements, size. 32 bytes, read once per
+// workgroup.
+struct CropDesc {
+    const uint8_t *grey;
+    const uint16_t *depth;
+    int32_t grey_pitch, depth_pitch;
+    int32_t w, h;
+};
+static_assert(sizeof(CropDesc) == 32, "CropDesc layout");
+
+// Feature geometry shared by every kernel launch of a context.
+struct FeatParams {
+    int32_t grid_x, grid_y;
+    int32_t nbins;        // 59 or 256
+    int32_t window;       // depth half-width in mm; <= 0 disables the mask
+    int32_t use_grey, use_depth;
+    int32_t nch;          // use_grey + use_depth
+    int32_t dim;          // nch * grid_x * grid_y * nbins
+};
+
+// Code -> bin tables, built on the host by construction (see tables.cpp).
+struct BinTables {
+    uint8_t bin[256];     // uniform-59 bin of a code, or the code itself for 256 bins
+};
+
+void build_uniform59(uint8_t out[256]);
+
+// Kernel launchers (features.hip). All return hipSuccess or the launch error.
+hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &fp,
+                           const uint8_t *d_bin_table, float *hist, uint32_t *counts,
+                           hipStream_t s);
+hipError_t launch_debug_codes(const CropDesc *crop, const FeatParams &fp, uint8_t *gcodes,
+                              uint8_t *dcodes, uint8_t *mask, int32_t w, int32_t h,
+                              hipStream_t s);
+
+// Scoring (score.hip).
+hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b,
+                            int32_t K, int32_t D, float *S, hipStream_t s);
+hipError_t launch_argmax(const float *S, int32_t N, int32_t K, int32_t *argmax, hipStream_t s);
+
+}  // namespace lbpf

@@ -1,0 +1,389 @@
+// C ABI of liblbpf.so (include/lbpf.h): contexts, host-side validation,
+// pinned staging of box tables, weights and dispatch to the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbpf_internal.h"
+
+using namespace lbpf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbpf_status fail(lbpf_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+lbpf_status fail_hip(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return LBPF_E_HIP;
+}
+
+#define HIP_TRY(expr, what)                        \
+    do {                                           \
+        hipError_t _e = (expr);                    \
+        if (_e != hipSuccess) return fail_hip(_e, what); \
+    } while (0)
+
+constexpr int kRing = 4;
+
+}  // namespace
+
+struct lbpf_ctx {
+    int device = 0;
+    lbpf_feature_cfg cfg{};
+    FeatParams fp{};
+    size_t budget = 0;   // 0 = unbounded
+    size_t used = 0;     // device bytes held by the context, its batches and weights
+    uint8_t *d_bins = nullptr;
+    CropDesc *h_stage[kRing] = {};
+    CropDesc *d_stage[kRing] = {};
+    hipEvent_t ev[kRing] = {};
+    int ring_next = 0;
+    float *d_scores = nullptr;  // scratch for argmax-only scoring
+    size_t scores_elems = 0;
+};
+
+struct lbpf_batch {
+    lbpf_ctx *ctx = nullptr;
+    CropDesc *d_crops = nullptr;
+    int32_t n = 0;
+    size_t bytes = 0;
+};
+
+struct lbpf_weights {
+    lbpf_ctx *ctx = nullptr;
+    int32_t K = 0, D = 0;
+    lbpf_precision prec = LBPF_FP32;
+    float *W = nullptr;
+    float *b = nullptr;
+    size_t bytes = 0;
+};
+
+namespace {
+
+constexpr size_t kScoreScratchElems = size_t(16) << 20;  // 64 MiB of FP32 scores
+
+bool charge(lbpf_ctx *ctx, size_t bytes) {
+    if (ctx->budget && ctx->used + bytes > ctx->budget) return false;
+    ctx->used += bytes;
+    return true;
+}
+
+// Resolve and validate a box table into crop descriptors.
+lbpf_status resolve(const lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                    const lbpf_box *boxes, int32_t n_boxes, std::vector<CropDesc> &out) {
+    if (n_boxes < 0 || n_images < 0) return fail(LBPF_E_INVALID, "negative count");
+    if (n_boxes > 0 && (!boxes || !images || n_images == 0))
+        return fail(LBPF_E_INVALID, "NULL image or box table");
+    out.resize((size_t)n_boxes);
+    for (int32_t i = 0; i < n_boxes; ++i) {
+        const lbpf_box &b = boxes[i];
+        char buf[160];
+        if (b.image < 0 || b.image >= n_images) {
+            snprintf(buf, sizeof buf, "box %d: image index %d out of range", i, b.image);
+            return fail(LBPF_E_INVALID, buf);
+        }
+        const lbpf_image &im = images[b.image];
+        if (!im.depth || (ctx->fp.use_grey && !im.grey)) {
+            snprintf(buf, sizeof buf, "box %d: image %d has a NULL plane", i, b.image);
+            return fail(LBPF_E_INVALID, buf);
+        }
+        if (im.width < 0 || im.height < 0 || im.depth_pitch < im.width ||
+            (ctx->fp.use_grey && im.grey_pitch < im.width)) {
+            snprintf(buf, sizeof buf, "image %d: bad size or pitch", b.image);
+            return fail(LBPF_E_INVALID, buf);
+        }
+        if (b.w < 3 || b.h < 3 || b.w > LBPF_MAX_SIDE || b.h > LBPF_MAX_SIDE || b.x < 0 ||
+            b.y < 0 || (int64_t)b.x + b.w > im.width || (int64_t)b.y + b.h > im.height) {
+            snprintf(buf, sizeof buf, "box %d (%d,%d,%d,%d) invalid for image %d (%dx%d)", i,
+                     b.x, b.y, b.w, b.h, b.image, im.width, im.height);
+            return fail(LBPF_E_INVALID, buf);
+        }
+        CropDesc &c = out[(size_t)i];
+        c.grey = im.grey ? im.grey + (size_t)b.y * im.grey_pitch + b.x : nullptr;
+        c.depth = im.depth + (size_t)b.y * im.depth_pitch + b.x;
+        c.grey_pitch = im.grey_pitch;
+        c.depth_pitch = im.depth_pitch;
+        c.w = b.w;
+        c.h = b.h;
+    }
+    return LBPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbpf_version(void) { return "lbpf 0.1.0 gfx950"; }
+
+const char *lbpf_status_string(lbpf_status s) {
+    switch (s) {
+        case LBPF_OK: return "LBPF_OK";
+        case LBPF_E_INVALID: return "LBPF_E_INVALID";
+        case LBPF_E_BUDGET: return "LBPF_E_BUDGET";
+        case LBPF_E_HIP: return "LBPF_E_HIP";
+        case LBPF_E_UNSUPPORTED: return "LBPF_E_UNSUPPORTED";
+    }
+    return "LBPF_E_UNKNOWN";
+}
+
+const char *lbpf_last_error(void) { return g_last_error.c_str(); }
+
+lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_budget_bytes) {
+    if (!out) return fail(LBPF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    lbpf_feature_cfg c = cfg ? *cfg : lbpf_feature_cfg{8, 8, LBPF_MAP_U59, 150, LBPF_MOD_BOTH};
+    if (c.grid_x < 1 || c.grid_y < 1 || c.grid_x * c.grid_y > 64)
+        return fail(LBPF_E_INVALID, "grid must satisfy 1 <= grid_x*grid_y <= 64");
+    if (c.mapping != LBPF_MAP_U59 && c.mapping != LBPF_MAP_FULL256)
+        return fail(LBPF_E_INVALID, "unknown mapping");
+    if (c.modality < LBPF_MOD_BOTH || c.modality > LBPF_MOD_DEPTH)
+        return fail(LBPF_E_INVALID, "unknown modality");
+
+    lbpf_ctx *ctx = new (std::nothrow) lbpf_ctx();
+    if (!ctx) return fail(LBPF_E_BUDGET, "out of host memory");
+    ctx->cfg = c;
+    ctx->budget = hbm_budget_bytes;
+    FeatParams &fp = ctx->fp;
+    fp.grid_x = c.grid_x;
+    fp.grid_y = c.grid_y;
+    fp.nbins = c.mapping == LBPF_MAP_U59 ? 59 : 256;
+    fp.window = c.depth_window_mm;
+    fp.use_grey = c.modality != LBPF_MOD_DEPTH;
+    fp.use_depth = c.modality != LBPF_MOD_GREY;
+    fp.nch = fp.use_grey + fp.use_depth;
+    fp.dim = fp.nch * c.grid_x * c.grid_y * fp.nbins;
+
+    auto cleanup = [&](lbpf_status s) {
+        lbpf_destroy(ctx);
+        return s;
+    };
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "hipGetDevice"));
+
+    const size_t stage_bytes = sizeof(CropDesc) * LBPF_MAX_BOXES_PER_CALL;
+    const size_t ws = 256 + kRing * stage_bytes + kScoreScratchElems * sizeof(float);
+    if (!charge(ctx, ws)) return cleanup(fail(LBPF_E_BUDGET, "workspace exceeds the HBM budget"));
+
+    uint8_t table[256];
+    if (c.mapping == LBPF_MAP_U59) {
+        build_uniform59(table);
+    } else {
+        for (int i = 0; i < 256; ++i) table[i] = (uint8_t)i;
+    }
+    if ((e = hipMalloc(&ctx->d_bins, 256)) != hipSuccess) return cleanup(fail_hip(e, "hipMalloc"));
+    if ((e = hipMemcpy(ctx->d_bins, table, 256, hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(fail_hip(e, "hipMemcpy"));
+    for (int i = 0; i < kRing; ++i) {
+        if ((e = hipHostMalloc((void **)&ctx->h_stage[i], stage_bytes, hipHostMallocDefault)) !=
+            hipSuccess)
+            return cleanup(fail_hip(e, "hipHostMalloc"));
+        if ((e = hipMalloc((void **)&ctx->d_stage[i], stage_bytes)) != hipSuccess)
+            return cleanup(fail_hip(e, "hipMalloc"));
+        if ((e = hipEventCreateWithFlags(&ctx->ev[i], hipEventDisableTiming)) != hipSuccess)
+            return cleanup(fail_hip(e, "hipEventCreate"));
+    }
+    if ((e = hipMalloc((void **)&ctx->d_scores, kScoreScratchElems * sizeof(float))) != hipSuccess)
+        return cleanup(fail_hip(e, "hipMalloc"));
+    ctx->scores_elems = kScoreScratchElems;
+    *out = ctx;
+    return LBPF_OK;
+}
+
+void lbpf_destroy(lbpf_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < kRing; ++i) {
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+        if (ctx->h_stage[i]) (void)hipHostFree(ctx->h_stage[i]);
+        if (ctx->d_stage[i]) (void)hipFree(ctx->d_stage[i]);
+    }
+    if (ctx->d_bins) (void)hipFree(ctx->d_bins);
+    if (ctx->d_scores) (void)hipFree(ctx->d_scores);
+    delete ctx;
+}
+
+int32_t lbpf_feature_dim(const lbpf_ctx *ctx) { return ctx ? ctx->fp.dim : -1; }
+
+lbpf_status lbpf_features(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                          const lbpf_box *boxes, int32_t n_boxes, float *hist,
+                          uint32_t *counts_opt, void *stream) {
+    if (!ctx) return fail(LBPF_E_INVALID, "ctx is NULL");
+    if (n_boxes > LBPF_MAX_BOXES_PER_CALL)
+        return fail(LBPF_E_BUDGET, "more boxes than LBPF_MAX_BOXES_PER_CALL");
+    if (n_boxes > 0 && !hist) return fail(LBPF_E_INVALID, "hist is NULL");
+    std::vector<CropDesc> crops;
+    lbpf_status st = resolve(ctx, images, n_images, boxes, n_boxes, crops);
+    if (st != LBPF_OK) return st;
+    if (n_boxes == 0) return LBPF_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int slot = ctx->ring_next;
+    ctx->ring_next = (slot + 1) % kRing;
+    HIP_TRY(hipEventSynchronize(ctx->ev[slot]), "hipEventSynchronize");
+    std::memcpy(ctx->h_stage[slot], crops.data(), sizeof(CropDesc) * crops.size());
+    HIP_TRY(hipMemcpyAsync(ctx->d_stage[slot], ctx->h_stage[slot], sizeof(CropDesc) * crops.size(),
+                           hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync");
+    HIP_TRY(launch_features(ctx->d_stage[slot], n_boxes, ctx->fp, ctx->d_bins, hist, counts_opt, s),
+            "feature kernel launch");
+    HIP_TRY(hipEventRecord(ctx->ev[slot], s), "hipEventRecord");
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_create(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                              const lbpf_box *boxes, int32_t n_boxes, lbpf_batch **out) {
+    if (!ctx || !out) return fail(LBPF_E_INVALID, "NULL argument");
+    *out = nullptr;
+    std::vector<CropDesc> crops;
+    lbpf_status st = resolve(ctx, images, n_images, boxes, n_boxes, crops);
+    if (st != LBPF_OK) return st;
+    const size_t bytes = sizeof(CropDesc) * (crops.size() ? crops.size() : 1);
+    if (!charge(ctx, bytes)) return fail(LBPF_E_BUDGET, "batch exceeds the HBM budget");
+    lbpf_batch *b = new (std::nothrow) lbpf_batch();
+    if (!b) {
+        ctx->used -= bytes;
+        return fail(LBPF_E_BUDGET, "out of host memory");
+    }
+    b->ctx = ctx;
+    b->n = n_boxes;
+    b->bytes = bytes;
+    hipError_t e = hipMalloc((void **)&b->d_crops, bytes);
+    if (e == hipSuccess && n_boxes > 0)
+        e = hipMemcpy(b->d_crops, crops.data(), sizeof(CropDesc) * crops.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        lbpf_batch_destroy(b);
+        return fail_hip(e, "batch upload");
+    }
+    *out = b;
+    return LBPF_OK;
+}
+
+void lbpf_batch_destroy(lbpf_batch *b) {
+    if (!b) return;
+    if (b->d_crops) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b->d_crops);
+    }
+    if (b->ctx) b->ctx->used -= b->bytes;
+    delete b;
+}
+
+int32_t lbpf_batch_size(const lbpf_batch *b) { return b ? b->n : -1; }
+
+lbpf_status lbpf_features_batch(lbpf_ctx *ctx, const lbpf_batch *batch, float *hist,
+                                uint32_t *counts_opt, void *stream) {
+    if (!ctx || !batch) return fail(LBPF_E_INVALID, "NULL argument");
+    if (batch->ctx != ctx) return fail(LBPF_E_INVALID, "batch belongs to another context");
+    if (batch->n == 0) return LBPF_OK;
+    if (!hist) return fail(LBPF_E_INVALID, "hist is NULL");
+    HIP_TRY(launch_features(batch->d_crops, batch->n, ctx->fp, ctx->d_bins, hist, counts_opt,
+                            (hipStream_t)stream),
+            "feature kernel launch");
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, int32_t K,
+                                lbpf_precision precision, lbpf_weights **out, void *stream) {
+    if (!ctx || !W || !b || !out || K < 1) return fail(LBPF_E_INVALID, "bad weights arguments");
+    *out = nullptr;
+    if (precision != LBPF_FP32) return fail(LBPF_E_UNSUPPORTED, "precision not built");
+    const int32_t D = ctx->fp.dim;
+    const size_t wbytes = sizeof(float) * (size_t)K * D, bbytes = sizeof(float) * (size_t)K;
+    if (!charge(ctx, wbytes + bbytes)) return fail(LBPF_E_BUDGET, "weights exceed the HBM budget");
+    lbpf_weights *w = new (std::nothrow) lbpf_weights();
+    if (!w) {
+        ctx->used -= wbytes + bbytes;
+        return fail(LBPF_E_BUDGET, "out of host memory");
+    }
+    w->ctx = ctx;
+    w->K = K;
+    w->D = D;
+    w->prec = precision;
+    w->bytes = wbytes + bbytes;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMalloc((void **)&w->W, wbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->b, bbytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(w->W, W, wbytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w->b, b, bbytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        lbpf_weights_destroy(w);
+        return fail_hip(e, "weights upload");
+    }
+    *out = w;
+    return LBPF_OK;
+}
+
+void lbpf_weights_destroy(lbpf_weights *w) {
+    if (!w) return;
+    if (w->W || w->b) (void)hipDeviceSynchronize();
+    if (w->W) (void)hipFree(w->W);
+    if (w->b) (void)hipFree(w->b);
+    if (w->ctx) w->ctx->used -= w->bytes;
+    delete w;
+}
+
+int32_t lbpf_weights_count(const lbpf_weights *w) { return w ? w->K : -1; }
+
+lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_weights *w,
+                       float *scores_opt, int32_t *argmax_opt, void *stream) {
+    if (!ctx || !w) return fail(LBPF_E_INVALID, "NULL argument");
+    if (w->ctx != ctx) return fail(LBPF_E_INVALID, "weights belong to another context");
+    if (N < 0) return fail(LBPF_E_INVALID, "N < 0");
+    if (!scores_opt && !argmax_opt) return fail(LBPF_E_INVALID, "no output requested");
+    if (N == 0) return LBPF_OK;
+    if (!hist) return fail(LBPF_E_INVALID, "hist is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (scores_opt) {
+        HIP_TRY(launch_score_f32(hist, N, w->W, w->b, w->K, w->D, scores_opt, s), "score launch");
+        if (argmax_opt) HIP_TRY(launch_argmax(scores_opt, N, w->K, argmax_opt, s), "argmax launch");
+        return LBPF_OK;
+    }
+    // Argmax only: score in chunks of rows through the context's scratch.
+    const int32_t rows = (int32_t)std::max<size_t>(1, ctx->scores_elems / (size_t)w->K);
+    for (int32_t n0 = 0; n0 < N; n0 += rows) {
+        const int32_t n = std::min(rows, N - n0);
+        HIP_TRY(launch_score_f32(hist + (size_t)n0 * w->D, n, w->W, w->b, w->K, w->D,
+                                 ctx->d_scores, s),
+                "score launch");
+        HIP_TRY(launch_argmax(ctx->d_scores, n, w->K, argmax_opt + n0, s), "argmax launch");
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_debug_codes(lbpf_ctx *ctx, const lbpf_image *image, const lbpf_box *box,
+                             uint8_t *grey_codes, uint8_t *depth_codes, uint8_t *mask,
+                             void *stream) {
+    if (!ctx || !image || !box || !grey_codes || !depth_codes || !mask)
+        return fail(LBPF_E_INVALID, "NULL argument");
+    lbpf_box b = *box;
+    b.image = 0;
+    std::vector<CropDesc> crops;
+    lbpf_status st = resolve(ctx, image, 1, &b, 1, crops);
+    if (st != LBPF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int slot = ctx->ring_next;
+    ctx->ring_next = (slot + 1) % kRing;
+    HIP_TRY(hipEventSynchronize(ctx->ev[slot]), "hipEventSynchronize");
+    std::memcpy(ctx->h_stage[slot], crops.data(), sizeof(CropDesc));
+    HIP_TRY(hipMemcpyAsync(ctx->d_stage[slot], ctx->h_stage[slot], sizeof(CropDesc),
+                           hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync");
+    HIP_TRY(launch_debug_codes(ctx->d_stage[slot], ctx->fp, grey_codes, depth_codes, mask, b.w,
+                               b.h, s),
+            "debug kernel launch");
+    HIP_TRY(hipEventRecord(ctx->ev[slot], s), "hipEventRecord");
+    return LBPF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+"""Thin ctypes binding of liblbpf.so (C ABI in include/lbpf.h).
+
+Argument marshalling only: torch CUDA tensors are passed as raw device
+pointers together with ``torch.cuda.current_stream()``; every step of the
+computation runs in the library's HIP kernels. There is no fallback: if the
+library is missing or fails to load, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+from typing import Sequence
+
+import numpy as np
+import torch
+
+_LIB_PATH = Path(__file__).resolve().parent / "liblbpf.so"
+
+LBPF_OK, LBPF_E_INVALID, LBPF_E_BUDGET, LBPF_E_HIP, LBPF_E_UNSUPPORTED = 0, -1, -2, -3, -4
+FP32, BF16, FP16, FP8_E4M3 = 0, 1, 2, 3
+MAP_U59, MAP_FULL256 = 0, 1
+MOD_BOTH, MOD_GREY, MOD_DEPTH = 0, 1, 2
+MAX_SIDE = 1024
+MAX_BOXES_PER_CALL = 65536
+
+_PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
+
+EXPORTS = [
+    "lbpf_version", "lbpf_create", "lbpf_destroy", "lbpf_feature_dim", "lbpf_features",
+    "lbpf_batch_create", "lbpf_batch_destroy", "lbpf_batch_size", "lbpf_features_batch",
+    "lbpf_weights_create", "lbpf_weights_destroy", "lbpf_weights_count", "lbpf_score",
+    "lbpf_debug_codes", "lbpf_status_string", "lbpf_last_error",
+]
+
+
+class LbpfError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{status_name(status)}: {detail}")
+        self.status = status
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("grey", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("grey_pitch", ctypes.c_int32), ("depth_pitch", ctypes.c_int32)]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_int32), ("x", ctypes.c_int32), ("y", ctypes.c_int32),
+                ("w", ctypes.c_int32), ("h", ctypes.c_int32)]
+
+
+class FeatureCfg(ctypes.Structure):
+    _fields_ = [("grid_x", ctypes.c_int32), ("grid_y", ctypes.c_int32),
+                ("mapping", ctypes.c_int32), ("depth_window_mm", ctypes.c_int32),
+                ("modality", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load liblbpf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _LIB_PATH.exists():
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                           "`python -m paper_1504_01883_amd.build`")
+    lib = ctypes.CDLL(str(_LIB_PATH))
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    st = ctypes.c_int
+    sig = {
+        "lbpf_version": (ctypes.c_char_p, []),
+        "lbpf_create": (st, [vp, vp, sz]),
+        "lbpf_destroy": (None, [vp]),
+        "lbpf_feature_dim": (i32, [vp]),
+        "lbpf_features": (st, [vp, vp, i32, vp, i32, vp, vp, vp]),
+        "lbpf_batch_create": (st, [vp, vp, i32, vp, i32, vp]),
+        "lbpf_batch_destroy": (None, [vp]),
+        "lbpf_batch_size": (i32, [vp]),
+        "lbpf_features_batch": (st, [vp, vp, vp, vp, vp]),
+        "lbpf_weights_create": (st, [vp, vp, vp, i32, st, vp, vp]),
+        "lbpf_weights_destroy": (None, [vp]),
+        "lbpf_weights_count": (i32, [vp]),
+        "lbpf_score": (st, [vp, vp, i32, vp, vp, vp, vp]),
+        "lbpf_debug_codes": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "lbpf_status_string": (ctypes.c_char_p, [st]),
+        "lbpf_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_name(status: int) -> str:
+    return load().lbpf_status_string(status).decode()
+
+
+def version() -> str:
+    return load().lbpf_version().decode()
+
+
+def _check(status: int):
+    if status != LBPF_OK:
+        raise LbpfError(status, load().lbpf_last_error().decode())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a CUDA (HIP) tensor")
+    return t.data_ptr()
+
+
+def _plane(t: torch.Tensor, elem_size: int):
+    if t.dim() != 2 or t.element_size() != elem_size or t.stride(1) != 1:
+        raise ValueError(f"expected a row-major 2-D plane of {elem_size}-byte elements")
+    return t.stride(0)
+
+
+def make_images(planes: Sequence[tuple]):
+    """ctypes array of lbpf_image from [(grey u8 [H,W] | None, depth u16 [H,W])] CUDA tensors."""
+    arr = (Image * max(1, len(planes)))()
+    for i, (g, z) in enumerate(planes):
+        zp = _plane(z, 2)
+        gp = _plane(g, 1) if g is not None else 0
+        arr[i] = Image(_dptr(g) if g is not None else None, _dptr(z), z.shape[1], z.shape[0],
+                       gp, zp)
+    return arr
+
+
+def make_boxes(boxes) -> ctypes.Array:
+    b = np.ascontiguousarray(np.asarray(boxes, np.int32).reshape(-1, 5))
+    arr = (Box * max(1, len(b)))()
+    ctypes.memmove(arr, b.ctypes.data, b.nbytes)
+    return arr, len(b)
+
+
+class Batch:
+    """A validated, device-resident box table (lbpf_batch)."""
+
+    def __init__(self, ctx: "Context", planes, boxes):
+        self._ctx = ctx
+        self._planes = list(planes)  # keep the tensors alive
+        imgs = make_images(self._planes)
+        bx, n = make_boxes(boxes)
+        h = ctypes.c_void_p()
+        _check(load().lbpf_batch_create(ctx._h, imgs, len(self._planes), bx, n, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if self._h:
+            load().lbpf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Weights:
+    """Enrolled identities (lbpf_weights)."""
+
+    def __init__(self, ctx: "Context", W: torch.Tensor, b: torch.Tensor, precision="fp32"):
+        W = W.to(torch.float32).contiguous()
+        b = b.to(torch.float32).contiguous()
+        if W.dim() != 2 or W.shape[1] != ctx.dim or b.shape != (W.shape[0],):
+            raise ValueError(f"W must be [K, {ctx.dim}] and b [K]")
+        self._ctx = ctx
+        self.K = W.shape[0]
+        self.precision = precision
+        h = ctypes.c_void_p()
+        _check(load().lbpf_weights_create(ctx._h, _dptr(W), _dptr(b), self.K,
+                                          _PRECISIONS[precision], ctypes.byref(h), _stream()))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            load().lbpf_weights_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """An lbpf_ctx on the current device."""
+
+    def __init__(self, grid=(8, 8), mapping=MAP_U59, window=150, modality=MOD_BOTH,
+                 budget_bytes=0):
+        cfg = FeatureCfg(grid[0], grid[1], mapping, window, modality)
+        h = ctypes.c_void_p()
+        _check(load().lbpf_create(ctypes.byref(h), ctypes.byref(cfg), budget_bytes))
+        self._h = h
+        self.dim = int(load().lbpf_feature_dim(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lbpf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def features(self, planes, boxes, with_counts=False, out=None, counts_out=None):
+        """Features of host-described boxes over device planes -> (hist, counts|None)."""
+        imgs = make_images(planes)
+        bx, n = make_boxes(boxes)
+        dev = planes[0][1].device if planes else torch.device("cuda")
+        hist = out if out is not None else torch.empty((n, self.dim), dtype=torch.float32,
+                                                       device=dev)
+        cnt = counts_out
+        if with_counts and cnt is None:
+            cnt = torch.empty((n, self.dim), dtype=torch.int32, device=dev)
+        _check(load().lbpf_features(self._h, imgs, len(planes), bx, n, _dptr(hist),
+                                    _dptr(cnt), _stream()))
+        return hist, cnt
+
+    def batch(self, planes, boxes) -> Batch:
+        return Batch(self, planes, boxes)
+
+    def features_batch(self, batch: Batch, out: torch.Tensor, counts_out: torch.Tensor | None = None):
+        if out.shape != (batch.n, self.dim) or out.dtype != torch.float32:
+            raise ValueError("out must be float32 [n, D]")
+        _check(load().lbpf_features_batch(self._h, batch._h, _dptr(out), _dptr(counts_out),
+                                          _stream()))
+        return out
+
+    def weights(self, W: torch.Tensor, b: torch.Tensor, precision="fp32") -> Weights:
+        return Weights(self, W, b, precision)
+
+    def score(self, hist: torch.Tensor, weights: Weights, want_scores=True, want_argmax=True,
+              scores_out=None, argmax_out=None):
+        if hist.dim() != 2 or hist.shape[1] != self.dim or hist.dtype != torch.float32:
+            raise ValueError("hist must be float32 [N, D]")
+        hist = hist.contiguous()
+        N = hist.shape[0]
+        S = scores_out
+        if want_scores and S is None:
+            S = torch.empty((N, weights.K), dtype=torch.float32, device=hist.device)
+        A = argmax_out
+        if want_argmax and A is None:
+            A = torch.empty((N,), dtype=torch.int32, device=hist.device)
+        _check(load().lbpf_score(self._h, _dptr(hist), N, weights._h, _dptr(S), _dptr(A),
+                                 _stream()))
+        return S, A
+
+    def debug_codes(self, grey: torch.Tensor, depth: torch.Tensor, box):
+        """Per-pixel (grey codes, depth codes, mask) of one box, as u8 [h, w] tensors."""
+        imgs = make_images([(grey, depth)])
+        x, y, w, h = (int(v) for v in box)
+        bx = Box(0, x, y, w, h)
+        outs = [torch.zeros((h, w), dtype=torch.uint8, device=depth.device) for _ in range(3)]
+        _check(load().lbpf_debug_codes(self._h, imgs, ctypes.byref(bx), *(_dptr(o) for o in outs),
+                                       _stream()))
+        return tuple(outs)
+
+
+def to_device_planes(grey: np.ndarray | None, depth: np.ndarray, device="cuda"):
+    """Copy host planes to the device as (grey u8, depth u16) tensors."""
+    z = torch.from_numpy(np.ascontiguousarray(depth, np.uint16)).to(device)
+    g = None
+    if grey is not None:
+        g = torch.from_numpy(np.ascontiguousarray(grey, np.uint8)).to(device)
+    return g, z

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+Integer results (codes, masks, counts) and the FP32 features are compared bit
+for bit; FP32 scores within 1e-5 of the oracle's FP64 scores relative to the
+dot product's condition scale; argmax exactly where the oracle's top-2 margin
+exceeds twice the score tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1504_01883_amd import lbpf, synth
+from tests.gpu_util import (host_planes, ragged_crops, require_gpu, score_tolerance,
+                            stacked_planes)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    c = lbpf.Context()
+    yield c
+    c.close()
+
+
+def _features_both(ctx, ref, grey, depth, **oracle_kw):
+    planes, boxes = stacked_planes(grey, depth)
+    hist, cnt = ctx.features(planes, boxes, with_counts=True)
+    torch.cuda.synchronize()
+    hp, _ = host_planes(grey, depth)
+    f, c, n_in = ref.features(hp, boxes, n_threads=8, **oracle_kw)
+    return hist.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), f, c, n_in
+
+
+def _assert_bitexact(gf, gc, f, c):
+    assert np.array_equal(gc, c), f"counts differ in {np.count_nonzero(gc != c)} places"
+    assert np.array_equal(gf.view(np.uint32), f.view(np.uint32)), "features differ"
+
+
+@pytest.mark.parametrize("h,w", [(64, 64), (128, 128), (3, 3), (4, 7), (37, 29), (255, 256)])
+def test_debug_codes_bitexact(ctx, ref, h, w):
+    g, z = synth.render_crop(w, h, synth.W_TINY, 1, 1000 + h + w)
+    dg, dz = lbpf.to_device_planes(g, z)
+    gc, zc, mk = ctx.debug_codes(dg, dz, (0, 0, w, h))
+    torch.cuda.synchronize()
+    rgc, rzc, rmk = ref.codes(g, z)
+    assert np.array_equal(gc.cpu().numpy(), rgc)
+    assert np.array_equal(zc.cpu().numpy(), rzc)
+    assert np.array_equal(mk.cpu().numpy(), rmk)
+
+
+def test_tiny_batch_bitexact(ctx, ref):
+    """100 crops of 64x64, the tiny workload."""
+    g, z, _ = synth.make_crops(100, 64, 64, synth.W_TINY, 10)
+    gf, gc, f, c, _ = _features_both(ctx, ref, g, z)
+    _assert_bitexact(gf, gc, f, c)
+
+
+def test_uniform_sample_bitexact(ctx, ref):
+    """A 96-crop sample of the 128x128 uniform workload."""
+    g, z, _ = synth.make_crops(96, 128, 128, synth.W_UNIFORM, 256)
+    gf, gc, f, c, _ = _features_both(ctx, ref, g, z)
+    _assert_bitexact(gf, gc, f, c)
+
+
+def test_ragged_bitexact(ctx, ref):
+    """Crops of independent sizes 3..300 (uneven cells), each in its own image."""
+    crops = ragged_crops(40, 7)
+    planes = [lbpf.to_device_planes(g, z) for g, z in crops]
+    boxes = [[i, 0, 0, z.shape[1], z.shape[0]] for i, (g, z) in enumerate(crops)]
+    hist, cnt = ctx.features(planes, boxes, with_counts=True)
+    torch.cuda.synchronize()
+    f, c, _ = ref.features(crops, boxes, n_threads=8)
+    _assert_bitexact(hist.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), f, c)
+
+
+def test_boxes_in_frame_bitexact(ctx, ref):
+    """Boxes read in place from a larger frame, including boxes on its edges."""
+    rng = np.random.default_rng(5)
+    H, W = 480, 640
+    G = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    Z = rng.integers(0, 3000, size=(H, W)).astype(np.uint16)
+    Z[rng.random((H, W)) < 0.3] = 0
+    boxes = [[0, 0, 0, 64, 64], [0, W - 100, H - 90, 100, 90], [0, 13, 77, 201, 150],
+             [0, 300, 0, 3, 480], [0, 0, 200, 640, 3], [0, 0, 0, 640, 480]]
+    dg, dz = lbpf.to_device_planes(G, Z)
+    hist, cnt = ctx.features([(dg, dz)], boxes, with_counts=True)
+    torch.cuda.synchronize()
+    f, c, _ = ref.features([(G, Z)], boxes, n_threads=8)
+    _assert_bitexact(hist.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), f, c)
+
+
+def test_degenerate_crops(ctx, ref):
+    """All-zero depth, constant planes, a single valid depth pixel, max side."""
+    crops = []
+    crops.append((np.full((20, 30), 9, np.uint8), np.zeros((20, 30), np.uint16)))
+    crops.append((np.full((16, 16), 200, np.uint8), np.full((16, 16), 65535, np.uint16)))
+    z = np.zeros((9, 9), np.uint16)
+    z[4, 4] = 1234
+    crops.append((np.arange(81, dtype=np.uint8).reshape(9, 9), z))
+    crops.append(synth.render_crop(1024, 40, synth.W_TINY, 2, 3000))
+    crops.append(synth.render_crop(33, 1024, synth.W_TINY, 3, 3001))
+    planes = [lbpf.to_device_planes(g, z) for g, z in crops]
+    boxes = [[i, 0, 0, z.shape[1], z.shape[0]] for i, (g, z) in enumerate(crops)]
+    hist, cnt = ctx.features(planes, boxes, with_counts=True)
+    torch.cuda.synchronize()
+    f, c, n_in = ref.features(crops, boxes)
+    _assert_bitexact(hist.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), f, c)
+    assert n_in[0] == 0 and not hist[0].any()
+
+
+@pytest.mark.parametrize("grid,mapping,window,modality", [
+    ((8, 8), lbpf.MAP_U59, 0, lbpf.MOD_BOTH),
+    ((8, 8), lbpf.MAP_U59, 150, lbpf.MOD_GREY),
+    ((8, 8), lbpf.MAP_U59, 150, lbpf.MOD_DEPTH),
+    ((4, 4), lbpf.MAP_FULL256, 150, lbpf.MOD_BOTH),
+    ((3, 5), lbpf.MAP_U59, 90, lbpf.MOD_BOTH),
+])
+def test_feature_variants_bitexact(ref, grid, mapping, window, modality):
+    require_gpu()
+    ctx = lbpf.Context(grid=grid, mapping=mapping, window=window, modality=modality)
+    g, z, _ = synth.make_crops(12, 70, 61, synth.W_TINY, 5)
+    gf, gc, f, c, _ = _features_both(ctx, ref, g, z, grid_x=grid[0], grid_y=grid[1],
+                                     mapping=mapping, window=window, modality=modality)
+    _assert_bitexact(gf, gc, f, c)
+    ctx.close()
+
+
+def test_batch_matches_direct_and_is_repeatable(ctx):
+    g, z, _ = synth.make_crops(64, 128, 128, synth.W_UNIFORM, 256)
+    planes, boxes = stacked_planes(g, z)
+    direct, _ = ctx.features(planes, boxes)
+    b = ctx.batch(planes, boxes)
+    out1 = torch.empty_like(direct)
+    out2 = torch.full_like(direct, -1.0)
+    ctx.features_batch(b, out1)
+    ctx.features_batch(b, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(direct, out1) and torch.equal(out1, out2)
+    b.close()
+
+
+def test_invalid_boxes_write_nothing(ctx):
+    g, z = lbpf.to_device_planes(np.zeros((32, 32), np.uint8), np.ones((32, 32), np.uint16))
+    out = torch.full((2, ctx.dim), 7.0, device="cuda")
+    for bad in ([[0, 30, 0, 3, 3], [0, 0, 0, 8, 8]], [[0, 0, 0, 2, 8]], [[1, 0, 0, 8, 8]]):
+        with pytest.raises(lbpf.LbpfError) as ei:
+            ctx.features([(g, z)], bad, out=out[: len(bad)])
+        assert ei.value.status == lbpf.LBPF_E_INVALID
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+
+
+def _check_scores(S, A, X, W, b, ref):
+    S64, A64 = ref.score_f64(X, W, b, n_threads=8)
+    tol = score_tolerance(X, W, b)
+    err = np.abs(S.astype(np.float64) - S64)
+    assert (err <= tol).all(), f"max err/tol = {(err / tol).max()}"
+    # argmax: exact over the GPU's own scores; equal to the oracle's where the
+    # oracle's top-2 margin exceeds twice the tolerance.
+    assert np.array_equal(A, np.argmax(S, axis=1))
+    top2 = np.sort(S64, axis=1)[:, -2:] if S64.shape[1] > 1 else None
+    if top2 is not None:
+        margin = top2[:, 1] - top2[:, 0]
+        clear = margin > 2 * tol.max(axis=1)
+        assert np.array_equal(A[clear], A64[clear])
+    return err.max()
+
+
+@pytest.mark.parametrize("N,K", [(1, 1), (100, 10), (257, 65), (4096, 256)])
+def test_scores_fp32(ctx, ref, N, K):
+    rng = np.random.default_rng(N * 1000 + K)
+    X = rng.random((N, ctx.dim), dtype=np.float32) / ctx.dim
+    W, b = synth.synthetic_weights(K, ctx.dim, synth.W_UNIFORM)
+    S, A = ctx.score(torch.from_numpy(X).cuda(), ctx.weights(torch.from_numpy(W).cuda(),
+                                                             torch.from_numpy(b).cuda()))
+    torch.cuda.synchronize()
+    _check_scores(S.cpu().numpy(), A.cpu().numpy(), X, W, b, ref)
+
+
+def test_scores_odd_dim(ref):
+    """D not a multiple of 4 (3x3 grid): the unvectorised operand path."""
+    require_gpu()
+    c = lbpf.Context(grid=(3, 3))
+    assert c.dim % 4 != 0
+    rng = np.random.default_rng(3)
+    X = rng.random((70, c.dim), dtype=np.float32)
+    W = rng.standard_normal((33, c.dim), dtype=np.float32)
+    b = rng.standard_normal(33).astype(np.float32)
+    S, A = c.score(torch.from_numpy(X).cuda(), c.weights(torch.from_numpy(W).cuda(),
+                                                         torch.from_numpy(b).cuda()))
+    torch.cuda.synchronize()
+    _check_scores(S.cpu().numpy(), A.cpu().numpy(), X, W, b, ref)
+    c.close()
+
+
+def test_argmax_only_matches_scores(ctx):
+    rng = np.random.default_rng(9)
+    X = torch.from_numpy(rng.random((300, ctx.dim), dtype=np.float32)).cuda()
+    W, b = synth.synthetic_weights(50, ctx.dim, synth.W_TINY)
+    wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda())
+    S, A = ctx.score(X, wts)
+    _, A2 = ctx.score(X, wts, want_scores=False)
+    torch.cuda.synchronize()
+    assert torch.equal(A, A2)
+
+
+def test_end_to_end_tiny_with_trained_weights(ctx, ref):
+    """The tiny workload end to end: 10 identities, 20 training crops each,
+    weights trained by the oracle in FP64 and shared as FP32; 100 test crops."""
+    tg, tz, tl = synth.make_training_set(10, 20, 64, 64, synth.W_TINY)
+    hp, tb = host_planes(tg, tz)
+    tf, _, _ = ref.features(hp, tb, n_threads=8)
+    W64, b64, _ = ref.train_ovr_f64(tf, tl, K=10, n_threads=8)
+    W, b = W64.astype(np.float32), b64.astype(np.float32)
+
+    g, z, labels = synth.make_crops(100, 64, 64, synth.W_TINY, 10)
+    planes, boxes = stacked_planes(g, z)
+    hist, _ = ctx.features(planes, boxes)
+    S, A = ctx.score(hist, ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda()))
+    torch.cuda.synchronize()
+    hp2, _ = host_planes(g, z)
+    f, _, _ = ref.features(hp2, boxes, n_threads=8)
+    assert np.array_equal(hist.cpu().numpy().view(np.uint32), f.view(np.uint32))
+    _check_scores(S.cpu().numpy(), A.cpu().numpy(), f, W, b, ref)
+    acc = float((A.cpu().numpy() == labels).mean())
+    print(f"tiny workload recognition accuracy (synthetic): {acc:.3f}")
+    assert acc >= 0.9
