@@ -1,15 +1,46 @@
 // Fused depth-masked LBP + regional histogram + L1 normalisation, gfx950.
 //
-// One workgroup (4 wave64) per face crop. Steps, all inside one launch:
-//   1. exact lower median of the crop's non-zero depth by a two-level radix
-//      select (high byte, then low byte) over 256-bin LDS histograms;
-//   2. for every interior pixel inside the depth window, the 3x3 LBP code of
-//      the grey and of the depth plane (Sec. 2.4, Eq. 2; p0 = top-left
-//      neighbour, clockwise, bit set when neighbour >= centre);
-//   3. code -> bin through a 256-entry LDS table (uniform-59 or identity);
-//   4. increments of the [channel][ry][rx][bin] histogram, kept in LDS;
-//   5. the row written once to HBM as count / T (IEEE single division) and,
-//      optionally, as raw counts.
+// One workgroup (4 wave64) per face crop; every step runs inside one launch:
+//   1. exact lower median m of the crop's non-zero depth (the depth region of
+//      interest of the paper's fusion), by a two-level radix select: a 256-bin
+//      histogram of the high bytes, then of the low bytes inside the selected
+//      high byte;
+//   2. for every interior pixel whose depth d satisfies d != 0 and
+//      |d - m| < window, the 3x3 LBP code of the grey and of the depth plane
+//      (Sec. 2.4, Eq. 2: neighbour p has weight 2^p and its bit is set when it
+//      is >= the centre; p0 = top-left neighbour, then clockwise);
+//   3. code -> uniform-59 bin through a 256-entry LDS table;
+//   4. increments of the [channel][ry][rx][bin] regional histogram (Eq. 3)
+//      held in LDS;
+//   5. the row written once to HBM as count / T, T = channels * n_in, each
+//      quotient the correctly rounded IEEE single division (and optionally the
+//      raw counts).
+//
+// Two kernels:
+//   k_features_fast  -- the default configuration (uniform-59 bins, both
+//                       channels, window 1..255 mm). Crops up to 256 px wide
+//                       take the fast path below; wider crops fall back to the
+//                       generic per-pixel loop inside the same launch.
+//   k_features_generic -- every other configuration (256 bins, one channel,
+//                       mask off, wide windows).
+//
+// Fast path, per crop:
+//   * Median: each thread loads 8 depth pixels per 16-byte load and adds them
+//     to the high-byte histogram as one count for the pixels sharing the
+//     first pixel's high byte (smooth depth makes that the common case) plus
+//     one count per other pixel, so contention on the LDS atomics stays low.
+//   * Codes: lanes own 4 adjacent columns and walk down a band of rows with a
+//     3-row register window. Each pixel is packed as (grey | d' << 16) with
+//     d' = clamp(d - (m - window), 0, 2 window) (0 for d = 0): clamping keeps
+//     every comparison against an in-window centre unchanged and makes the
+//     depth fit 9 bits, so ONE packed 16-bit subtraction per neighbour yields
+//     both channels' comparisons. For a negative difference the high bits of
+//     each 16-bit half are all ones (bits 8..15 for grey, 9..15 for d'), so
+//     one AND-OR per neighbour deposits the grey bit and the depth bit into
+//     distinct positions of one accumulator. Halo columns come from the
+//     neighbouring lanes through DPP wave shifts.
+//   * Normalisation: count / T is tabulated once per crop for every count a
+//     cell can hold, then the row is written by table lookup.
 #include "lbpf_internal.h"
 
 namespace lbpf {
@@ -18,10 +49,42 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kFastMaxW = 256;    // 64 lanes x 4 columns
+constexpr int kQuot = 1088;       // tabulated quotients (cells up to 32 x 34 px)
+constexpr int kU59 = 59;
 
 // Neighbour p of the centre (y, x) is (y + kDy[p], x + kDx[p]).
 __constant__ int8_t kDy[8] = {-1, -1, -1, 0, 1, 1, 1, 0};
 __constant__ int8_t kDx[8] = {-1, 0, 1, 1, 1, 0, -1, -1};
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_sub_sat(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, a),
+                                                                      __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t ld_u32(const void *p) {
+    uint32_t v;
+    __builtin_memcpy(&v, p, 4);
+    return v;
+}
+__device__ __forceinline__ uint2 ld_u64(const void *p) {
+    uint2 v;
+    __builtin_memcpy(&v, p, 8);
+    return v;
+}
+__device__ __forceinline__ uint4 ld_u128(const void *p) {
+    uint4 v;
+    __builtin_memcpy(&v, p, 16);
+    return v;
+}
 
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
 #pragma unroll
@@ -32,78 +95,115 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
     return v;
 }
 
-// Given a 256-bin histogram in LDS and a 0-based rank, find the bin holding
-// that rank and the rank inside the bin. Runs on wave 0 only.
-__device__ __forceinline__ void select_bin(const uint32_t *h, uint32_t rank, int lane,
-                                           int32_t *out_bin, uint32_t *out_rank,
-                                           uint32_t *out_total) {
-    uint32_t c0 = h[4 * lane + 0], c1 = h[4 * lane + 1], c2 = h[4 * lane + 2],
-             c3 = h[4 * lane + 3];
-    uint32_t s = c0 + c1 + c2 + c3;
-    uint32_t incl = wave_inclusive_scan(s, lane);
-    uint32_t excl = incl - s;
-    uint32_t total = __shfl(incl, 63, 64);
-    if (lane == 0) *out_total = total;
-    if (rank < total && excl <= rank && rank < incl) {
-        uint32_t r = rank - excl;
-        int b = 4 * lane;
-        if (r >= c0) { r -= c0; b += 1;
-            if (r >= c1) { r -= c1; b += 1;
-                if (r >= c2) { r -= c2; b += 1; } } }
-        *out_bin = b;
-        *out_rank = r;
-    }
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 struct MedianScratch {
     uint32_t hist[256];
     int32_t bin;
     uint32_t rank;
-    uint32_t total;
 };
 
-// Exact lower median of the non-zero depth of the crop, or -1 when every
-// depth pixel is 0. All threads of the block must call it.
+// On wave 0: find the bin of a 256-bin LDS histogram that holds 0-based rank
+// `rank`, and the rank inside that bin. rank >= total leaves ms.bin at -1.
+__device__ __forceinline__ void select_bin(MedianScratch &ms, uint32_t rank, int lane) {
+    const uint32_t c0 = ms.hist[4 * lane + 0], c1 = ms.hist[4 * lane + 1],
+                   c2 = ms.hist[4 * lane + 2], c3 = ms.hist[4 * lane + 3];
+    const uint32_t s = c0 + c1 + c2 + c3;
+    const uint32_t incl = wave_inclusive_scan(s, lane);
+    const uint32_t excl = incl - s;
+    if (lane == 0) ms.bin = -1;
+    if (excl <= rank && rank < incl) {
+        uint32_t r = rank - excl;
+        int b = 4 * lane;
+        if (r >= c0) {
+            r -= c0;
+            b += 1;
+            if (r >= c1) {
+                r -= c1;
+                b += 1;
+                if (r >= c2) {
+                    r -= c2;
+                    b += 1;
+                }
+            }
+        }
+        ms.bin = b;
+        ms.rank = r;
+    }
+}
+
+// Load the 8 depth pixels x0..x0+7 of a row (zeros past the crop's width).
+__device__ __forceinline__ void load8(const uint16_t *row, int x0, int w, uint32_t v[8]) {
+    if (x0 + 8 <= w) {
+        const uint4 q = ld_u128(row + x0);
+        v[0] = q.x & 0xFFFFu; v[1] = q.x >> 16;
+        v[2] = q.y & 0xFFFFu; v[3] = q.y >> 16;
+        v[4] = q.z & 0xFFFFu; v[5] = q.z >> 16;
+        v[6] = q.w & 0xFFFFu; v[7] = q.w >> 16;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (x0 + i < w) ? row[x0 + i] : 0u;
+    }
+}
+
+// Exact lower median of the non-zero depth values of the crop, -1 if none.
+// All threads of the block call it.
 __device__ int32_t crop_median(const CropDesc &c, MedianScratch &ms) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cpr = (c.w + 7) >> 3;              // 8-pixel chunks per row (<= 128)
+    const int rows_par = kThreads / cpr;         // rows visited in parallel
+    const int cx = tid % cpr, ry0 = tid / cpr;
+    const bool act = ry0 < rows_par;
     for (int i = tid; i < 256; i += kThreads) ms.hist[i] = 0;
     __syncthreads();
-    for (int y = wave; y < c.h; y += kWaves) {
-        const uint16_t *row = c.depth + (size_t)y * c.depth_pitch;
-        for (int x = lane; x < c.w; x += 64) {
-            uint32_t d = row[x];
-            if (d != 0) atomicAdd(&ms.hist[d >> 8], 1u);
+    if (act) {
+        for (int y = ry0; y < c.h; y += rows_par) {
+            uint32_t v[8];
+            load8(c.depth + (size_t)y * c.depth_pitch, 8 * cx, c.w, v);
+            const uint32_t key = (v[3] ? v[3] : v[4]) >> 8;
+            uint32_t same = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) same += (v[i] != 0 && (v[i] >> 8) == key) ? 1u : 0u;
+            if (same) atomicAdd(&ms.hist[key], same);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (v[i] != 0 && (v[i] >> 8) != key) atomicAdd(&ms.hist[v[i] >> 8], 1u);
         }
     }
     __syncthreads();
     if (wave == 0) {
-        // rank (n-1)/2 of the non-zero values; the total is found in the scan.
-        uint32_t s = ms.hist[4 * lane] + ms.hist[4 * lane + 1] + ms.hist[4 * lane + 2] +
-                     ms.hist[4 * lane + 3];
-        uint32_t tot = s;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
-        if (lane == 0) ms.bin = -1;
-        if (tot > 0) select_bin(ms.hist, (tot - 1) / 2, lane, &ms.bin, &ms.rank, &ms.total);
-    }
-    __syncthreads();
-    const int32_t hi = ms.bin;
-    if (hi < 0) return -1;
-    const uint32_t rank_in_hi = ms.rank;
-    __syncthreads();
-    for (int i = tid; i < 256; i += kThreads) ms.hist[i] = 0;
-    __syncthreads();
-    for (int y = wave; y < c.h; y += kWaves) {
-        const uint16_t *row = c.depth + (size_t)y * c.depth_pitch;
-        for (int x = lane; x < c.w; x += 64) {
-            uint32_t d = row[x];
-            if (d != 0 && (int32_t)(d >> 8) == hi) atomicAdd(&ms.hist[d & 255u], 1u);
+        const uint32_t tot = wave_sum(ms.hist[4 * lane] + ms.hist[4 * lane + 1] +
+                                      ms.hist[4 * lane + 2] + ms.hist[4 * lane + 3]);
+        if (tot > 0) {
+            select_bin(ms, (tot - 1) / 2, lane);
+        } else if (lane == 0) {
+            ms.bin = -1;
         }
     }
     __syncthreads();
-    if (wave == 0) select_bin(ms.hist, rank_in_hi, lane, &ms.bin, &ms.rank, &ms.total);
+    const int32_t hi = ms.bin;
+    const uint32_t rank_in_hi = ms.rank;
+    if (hi < 0) return -1;
     __syncthreads();
-    int32_t m = (hi << 8) | ms.bin;
+    for (int i = tid; i < 256; i += kThreads) ms.hist[i] = 0;
+    __syncthreads();
+    if (act) {
+        for (int y = ry0; y < c.h; y += rows_par) {
+            uint32_t v[8];
+            load8(c.depth + (size_t)y * c.depth_pitch, 8 * cx, c.w, v);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (v[i] != 0 && (int32_t)(v[i] >> 8) == hi) atomicAdd(&ms.hist[v[i] & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    if (wave == 0) select_bin(ms, rank_in_hi, lane);
+    __syncthreads();
+    const int32_t m = (hi << 8) | ms.bin;
     __syncthreads();
     return m;
 }
@@ -111,7 +211,7 @@ __device__ int32_t crop_median(const CropDesc &c, MedianScratch &ms) {
 __device__ __forceinline__ bool centre_in_mask(uint32_t d, int32_t m, int32_t window) {
     if (window <= 0) return true;
     if (m < 0 || d == 0) return false;
-    int32_t diff = (int32_t)d - m;
+    const int32_t diff = (int32_t)d - m;
     return diff < window && -diff < window;
 }
 
@@ -121,73 +221,268 @@ __device__ __forceinline__ uint32_t lbp_code(const T *p, int32_t pitch, int y, i
     uint32_t code = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        uint32_t g = p[(size_t)(y + kDy[k]) * pitch + (x + kDx[k])];
+        const uint32_t g = p[(size_t)(y + kDy[k]) * pitch + (x + kDx[k])];
         code |= (g >= c ? 1u : 0u) << k;
     }
     return code;
 }
 
-__global__ __launch_bounds__(kThreads) void k_features_v1(const CropDesc *__restrict__ crops,
-                                                          FeatParams fp,
-                                                          const uint8_t *__restrict__ bin_table,
-                                                          float *__restrict__ hist,
-                                                          uint32_t *__restrict__ counts) {
-    extern __shared__ uint32_t sh_hist[];  // fp.dim counters
+// Per-pixel histogram loop for any crop and configuration: each thread takes
+// pixels in row order and increments its bins with LDS atomics.
+__device__ void lbp_hist_generic(const CropDesc &c, const FeatParams &fp, int32_t m,
+                                 const uint8_t *sh_bin, const uint8_t *sh_rowband,
+                                 const uint8_t *sh_colband, uint32_t *sh_hist) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cells = fp.grid_x * fp.grid_y;
+    const int nb = fp.nbins;
+    for (int y = 1 + wave; y <= c.h - 2; y += kWaves) {
+        const int rowcell = sh_rowband[y] * fp.grid_x;
+        for (int x = 1 + lane; x <= c.w - 2; x += 64) {
+            const uint32_t dc = c.depth[(size_t)y * c.depth_pitch + x];
+            if (!centre_in_mask(dc, m, fp.window)) continue;
+            const int cell = rowcell + sh_colband[x];
+            int ch = 0;
+            if (fp.use_grey) {
+                const uint32_t code = lbp_code(c.grey, c.grey_pitch, y, x);
+                atomicAdd(&sh_hist[cell * nb + sh_bin[code]], 1u);
+                ch = 1;
+            }
+            if (fp.use_depth) {
+                const uint32_t code = lbp_code(c.depth, c.depth_pitch, y, x);
+                atomicAdd(&sh_hist[(ch * cells + cell) * nb + sh_bin[code]], 1u);
+            }
+        }
+    }
+}
+
+// Load columns x0..x0+3 of one row: grey bytes packed in G, depth u16 pairs
+// in Z0 (x0, x0+1) and Z1 (x0+2, x0+3). Columns past the crop read column
+// w-1 (their results are never used).
+__device__ __forceinline__ void load_group(const uint8_t *grow, const uint16_t *drow, int x0,
+                                           int w, uint32_t &G, uint32_t &Z0, uint32_t &Z1) {
+    if (x0 + 4 <= w) {
+        G = ld_u32(grow + x0);
+        const uint2 z = ld_u64(drow + x0);
+        Z0 = z.x;
+        Z1 = z.y;
+    } else {
+        const int x1 = min(x0 + 1, w - 1), x2 = min(x0 + 2, w - 1), x3 = min(x0 + 3, w - 1);
+        const int xa = min(x0, w - 1);
+        G = (uint32_t)grow[xa] | ((uint32_t)grow[x1] << 8) | ((uint32_t)grow[x2] << 16) |
+            ((uint32_t)grow[x3] << 24);
+        Z0 = (uint32_t)drow[xa] | ((uint32_t)drow[x1] << 16);
+        Z1 = (uint32_t)drow[x2] | ((uint32_t)drow[x3] << 16);
+    }
+}
+
+// d' = 0 for d == 0, else clamp(d - lo, 0, span), on a pair of u16.
+__device__ __forceinline__ uint32_t to_window(uint32_t z, int32_t lo, uint32_t lolo, uint32_t span2) {
+    if (lo >= 0) return pk_min(pk_sub_sat(z, lolo), span2);
+    const uint32_t a = z & 0xFFFFu, b = z >> 16;
+    const int32_t span = (int32_t)(span2 & 0xFFFFu);
+    const uint32_t da = a ? (uint32_t)min((int32_t)a - lo, span) : 0u;
+    const uint32_t db = b ? (uint32_t)min((int32_t)b - lo, span) : 0u;
+    return da | (db << 16);
+}
+
+// Row of 6 packed pixels (grey | d' << 16): [x0-1, x0, x0+1, x0+2, x0+3, x0+4].
+struct Row6 {
+    uint32_t p[6];
+};
+
+__device__ __forceinline__ Row6 make_row(uint32_t G, uint32_t D0, uint32_t D1) {
+    Row6 r;
+    r.p[1] = __builtin_amdgcn_perm(G, D0, 0x01000C04u);
+    r.p[2] = __builtin_amdgcn_perm(G, D0, 0x03020C05u);
+    r.p[3] = __builtin_amdgcn_perm(G, D1, 0x01000C06u);
+    r.p[4] = __builtin_amdgcn_perm(G, D1, 0x03020C07u);
+    // Left halo = previous lane's last pixel, right halo = next lane's first.
+    r.p[0] = __builtin_amdgcn_update_dpp(0u, r.p[4], 0x138, 0xF, 0xF, false);  // wave_shr:1
+    r.p[5] = __builtin_amdgcn_update_dpp(0u, r.p[1], 0x130, 0xF, 0xF, false);  // wave_shl:1
+    return r;
+}
+
+// Comparison bits of the centre A/B/C[j] (rows y-1, y, y+1): grey bit of
+// neighbour p at 8+p, depth bit of neighbour p at 25+p (p < 7) and of p7 at
+// 24. A set bit means the neighbour is BELOW the centre.
+__device__ __forceinline__ uint32_t compare_bits(const Row6 &A, const Row6 &B, const Row6 &C, int j) {
+    const uint32_t c = B.p[j];
+    const uint32_t d0 = pk_sub(A.p[j - 1], c), d1 = pk_sub(A.p[j], c), d2 = pk_sub(A.p[j + 1], c);
+    const uint32_t d3 = pk_sub(B.p[j + 1], c), d4 = pk_sub(C.p[j + 1], c), d5 = pk_sub(C.p[j], c);
+    const uint32_t d6 = pk_sub(C.p[j - 1], c), d7 = pk_sub(B.p[j - 1], c);
+    uint32_t acc = (d0 & 0x02000100u) | (d1 & 0x04000200u);
+    acc |= d2 & 0x08000400u;
+    acc |= d3 & 0x10000800u;
+    acc |= d4 & 0x20001000u;
+    acc |= d5 & 0x40002000u;
+    acc |= d6 & 0x80004000u;
+    acc |= d7 & 0x00008000u;
+    acc |= (d7 >> 7) & 0x01000000u;
+    return acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__restrict__ crops,
+                                                            FeatParams fp,
+                                                            const uint8_t *__restrict__ tables,
+                                                            float *__restrict__ hist,
+                                                            uint32_t *__restrict__ counts) {
+    // fp.dim = 2 * cells * 59 counters, then 64 per-lane discard slots.
+    __shared__ uint32_t sh_hist[2 * 64 * kU59 + 64];
+    __shared__ MedianScratch ms;
+    __shared__ uint8_t sh_bin[256];      // code -> bin
+    __shared__ uint8_t sh_lut_g[256];    // grey comparison byte -> bin
+    __shared__ uint8_t sh_lut_d[256];    // depth comparison byte -> bin
+    __shared__ uint8_t sh_rowband[LBPF_MAX_SIDE];
+    __shared__ uint8_t sh_colband[LBPF_MAX_SIDE];
+    __shared__ float sh_q[kQuot];
+    __shared__ uint32_t sh_red[kWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const CropDesc c = crops[blockIdx.x];
+    const int gx = fp.grid_x, gy = fp.grid_y, cells = gx * gy;
+    const int dim = fp.dim;
+
+    for (int i = tid; i < dim + 64; i += kThreads) sh_hist[i] = 0;
+    for (int i = tid; i < 256; i += kThreads) {
+        sh_bin[i] = tables[i];
+        sh_lut_g[i] = tables[256 + i];
+        sh_lut_d[i] = tables[512 + i];
+    }
+    // Coordinate y lies in band floor(((y + 1) g - 1) / n) of a side of length n.
+    for (int y = tid; y < c.h; y += kThreads) sh_rowband[y] = (uint8_t)(((y + 1) * gy - 1) / c.h);
+    for (int x = tid; x < c.w; x += kThreads) sh_colband[x] = (uint8_t)(((x + 1) * gx - 1) / c.w);
+
+    const int32_t m = crop_median(c, ms);  // ends with a barrier
+
+    if (c.w <= kFastMaxW) {
+        if (m >= 0) {
+            const int L = (c.w + 3) >> 2;         // lanes per stream (<= 64)
+            const int spw = 64 / L;               // streams per wave
+            const int sw = lane / L;              // stream of this lane within the wave
+            const int x0 = 4 * (lane - sw * L);
+            const int S = kWaves * spw;
+            const int s = wave * spw + (sw < spw ? sw : 0);
+            const int rows = c.h - 2;
+            const int yb = 1 + (s * rows) / S;
+            const int ye = (sw < spw) ? 1 + ((s + 1) * rows) / S : yb;
+
+            const int32_t lo = m - fp.window;
+            const uint32_t lolo = (uint32_t)(lo & 0xFFFF) * 0x10001u;
+            const uint32_t span2 = (uint32_t)(2 * fp.window) * 0x10001u;
+            const uint32_t in_hi = (uint32_t)(2 * fp.window - 1) << 16;
+
+            // Column part of each pixel's histogram index, and the discard slot.
+            int colpart[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) colpart[k] = sh_colband[min(x0 + k, c.w - 1)] * kU59;
+            const int discard = dim + lane;
+            const int dep_off = cells * kU59;
+
+            const uint8_t *gbase = c.grey;
+            const uint16_t *dbase = c.depth;
+            Row6 A, B, C;
+            if (yb < ye) {
+                uint32_t G, Z0, Z1;
+                load_group(gbase + (size_t)(yb - 1) * c.grey_pitch,
+                           dbase + (size_t)(yb - 1) * c.depth_pitch, x0, c.w, G, Z0, Z1);
+                A = make_row(G, to_window(Z0, lo, lolo, span2), to_window(Z1, lo, lolo, span2));
+                load_group(gbase + (size_t)yb * c.grey_pitch, dbase + (size_t)yb * c.depth_pitch,
+                           x0, c.w, G, Z0, Z1);
+                B = make_row(G, to_window(Z0, lo, lolo, span2), to_window(Z1, lo, lolo, span2));
+            }
+            for (int y = yb; y < ye; ++y) {
+                uint32_t G, Z0, Z1;
+                load_group(gbase + (size_t)(y + 1) * c.grey_pitch,
+                           dbase + (size_t)(y + 1) * c.depth_pitch, x0, c.w, G, Z0, Z1);
+                C = make_row(G, to_window(Z0, lo, lolo, span2), to_window(Z1, lo, lolo, span2));
+                const int rowpart = sh_rowband[y] * gx * kU59;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t bits = compare_bits(A, B, C, k + 1);
+                    const int x = x0 + k;
+                    const bool in = (B.p[k + 1] - 0x10000u) < in_hi && x >= 1 && x <= c.w - 2;
+                    const int base = rowpart + colpart[k];
+                    const int ig = in ? base + sh_lut_g[(bits >> 8) & 0xFFu] : discard;
+                    const int id = in ? dep_off + base + sh_lut_d[bits >> 24] : discard;
+                    atomicAdd(&sh_hist[ig], 1u);
+                    atomicAdd(&sh_hist[id], 1u);
+                }
+                A = B;
+                B = C;
+            }
+        }
+    } else {
+        lbp_hist_generic(c, fp, m, sh_bin, sh_rowband, sh_colband, sh_hist);
+    }
+    __syncthreads();
+
+    // n_in = total of the grey half; T = 2 n_in.
+    uint32_t part = 0;
+    for (int i = tid; i < cells * kU59; i += kThreads) part += sh_hist[i];
+    part = wave_sum(part);
+    if (lane == 0) sh_red[wave] = part;
+    __syncthreads();
+    uint32_t n_in = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) n_in += sh_red[w];
+    const float T = (float)(2u * n_in);
+    const int maxc = ((c.h + gy - 1) / gy) * ((c.w + gx - 1) / gx);  // cell capacity bound
+    const bool tab = maxc < kQuot;
+    if (tab) {
+        for (int v = tid; v <= maxc; v += kThreads) sh_q[v] = n_in ? (float)v / T : 0.0f;
+        __syncthreads();
+    }
+    float *out = hist + (size_t)blockIdx.x * dim;
+    uint32_t *cout = counts ? counts + (size_t)blockIdx.x * dim : nullptr;
+    for (int i = tid; i < dim; i += kThreads) {
+        const uint32_t v = sh_hist[i];
+        out[i] = tab ? sh_q[v] : (n_in ? (float)v / T : 0.0f);
+        if (cout) cout[i] = v;
+    }
+}
+
+// Any configuration: dynamic LDS holds fp.dim counters.
+__global__ __launch_bounds__(kThreads) void k_features_generic(const CropDesc *__restrict__ crops,
+                                                               FeatParams fp,
+                                                               const uint8_t *__restrict__ tables,
+                                                               float *__restrict__ hist,
+                                                               uint32_t *__restrict__ counts) {
+    extern __shared__ uint32_t sh_hist[];
     __shared__ MedianScratch ms;
     __shared__ uint8_t sh_bin[256];
     __shared__ uint8_t sh_rowband[LBPF_MAX_SIDE];
     __shared__ uint8_t sh_colband[LBPF_MAX_SIDE];
-    __shared__ uint32_t sh_nin[kWaves];
+    __shared__ uint32_t sh_red[kWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const CropDesc c = crops[blockIdx.x];
 
     for (int i = tid; i < fp.dim; i += kThreads) sh_hist[i] = 0;
-    for (int i = tid; i < 256; i += kThreads) sh_bin[i] = bin_table[i];
-    // Band of each row/column: band r covers [floor(r n / g), floor((r+1) n / g)),
-    // so coordinate y lies in band floor(((y + 1) g - 1) / n).
+    for (int i = tid; i < 256; i += kThreads) sh_bin[i] = tables[i];
     for (int y = tid; y < c.h; y += kThreads) sh_rowband[y] = (uint8_t)(((y + 1) * fp.grid_y - 1) / c.h);
     for (int x = tid; x < c.w; x += kThreads) sh_colband[x] = (uint8_t)(((x + 1) * fp.grid_x - 1) / c.w);
-
+    __syncthreads();
     const int32_t m = fp.window > 0 ? crop_median(c, ms) : -1;
+
+    lbp_hist_generic(c, fp, m, sh_bin, sh_rowband, sh_colband, sh_hist);
     __syncthreads();
 
-    const int cells = fp.grid_x * fp.grid_y;
-    const int nb = fp.nbins;
-    uint32_t n_in = 0;
-    for (int y = 1 + wave; y <= c.h - 2; y += kWaves) {
-        const int rowcell = sh_rowband[y] * fp.grid_x;
-        for (int x = 1 + lane; x <= c.w - 2; x += 64) {
-            uint32_t dc = c.depth[(size_t)y * c.depth_pitch + x];
-            if (!centre_in_mask(dc, m, fp.window)) continue;
-            n_in += 1;
-            const int cell = rowcell + sh_colband[x];
-            int ch = 0;
-            if (fp.use_grey) {
-                uint32_t code = lbp_code(c.grey, c.grey_pitch, y, x);
-                atomicAdd(&sh_hist[cell * nb + sh_bin[code]], 1u);
-                ch = 1;
-            }
-            if (fp.use_depth) {
-                uint32_t code = lbp_code(c.depth, c.depth_pitch, y, x);
-                atomicAdd(&sh_hist[(ch * cells + cell) * nb + sh_bin[code]], 1u);
-            }
-        }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) n_in += __shfl_xor(n_in, off, 64);
-    if (lane == 0) sh_nin[wave] = n_in;
+    const int per_ch = fp.grid_x * fp.grid_y * fp.nbins;
+    uint32_t part = 0;
+    for (int i = tid; i < per_ch; i += kThreads) part += sh_hist[i];
+    part = wave_sum(part);
+    if (lane == 0) sh_red[wave] = part;
     __syncthreads();
-    uint32_t total_in = 0;
+    uint32_t n_in = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) total_in += sh_nin[w];
-    const float T = (float)(fp.nch * total_in);
+    for (int w = 0; w < kWaves; ++w) n_in += sh_red[w];
+    const float T = (float)(fp.nch * n_in);
 
     float *out = hist + (size_t)blockIdx.x * fp.dim;
     uint32_t *cout = counts ? counts + (size_t)blockIdx.x * fp.dim : nullptr;
     for (int i = tid; i < fp.dim; i += kThreads) {
-        uint32_t v = sh_hist[i];
-        out[i] = total_in ? (float)v / T : 0.0f;
+        const uint32_t v = sh_hist[i];
+        out[i] = n_in ? (float)v / T : 0.0f;
         if (cout) cout[i] = v;
     }
 }
@@ -199,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_debug_codes(const CropDesc *__rest
     const CropDesc c = *crop;
     const int32_t m = fp.window > 0 ? crop_median(c, ms) : -1;
     for (int i = threadIdx.x; i < c.w * c.h; i += kThreads) {
-        int y = i / c.w, x = i % c.w;
+        const int y = i / c.w, x = i % c.w;
         uint8_t g = 0, d = 0, k = 0;
         if (y >= 1 && y <= c.h - 2 && x >= 1 && x <= c.w - 2) {
             if (c.grey) g = (uint8_t)lbp_code(c.grey, c.grey_pitch, y, x);
@@ -214,22 +509,32 @@ __global__ __launch_bounds__(kThreads) void k_debug_codes(const CropDesc *__rest
 
 }  // namespace
 
+bool fast_path_ok(const FeatParams &fp) {
+    return fp.nbins == kU59 && fp.use_grey && fp.use_depth && fp.window >= 1 &&
+           fp.window <= 255 && fp.grid_x * fp.grid_y <= 64;
+}
+
 hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &fp,
-                           const uint8_t *d_bin_table, float *hist, uint32_t *counts,
+                           const uint8_t *d_tables, float *hist, uint32_t *counts,
                            hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (fast_path_ok(fp)) {
+        hipLaunchKernelGGL(k_features_fast, dim3(n), dim3(kThreads), 0, s, crops, fp, d_tables,
+                           hist, counts);
+        return hipGetLastError();
+    }
     const size_t shmem = (size_t)fp.dim * sizeof(uint32_t);
     // Above 64 KiB of dynamic LDS (the 256-bin mapping) the kernel must opt in.
     static size_t shmem_limit = 64 * 1024;
     if (shmem > shmem_limit) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_features_v1,
+        hipError_t e = hipFuncSetAttribute((const void *)k_features_generic,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)shmem);
         if (e != hipSuccess) return e;
         shmem_limit = shmem;
     }
-    hipLaunchKernelGGL(k_features_v1, dim3(n), dim3(kThreads), shmem, s, crops, fp, d_bin_table,
-                       hist, counts);
+    hipLaunchKernelGGL(k_features_generic, dim3(n), dim3(kThreads), shmem, s, crops, fp,
+                       d_tables, hist, counts);
     return hipGetLastError();
 }
 

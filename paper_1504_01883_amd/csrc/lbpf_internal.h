@@ -30,16 +30,14 @@ struct FeatParams {
     int32_t dim;          // nch * grid_x * grid_y * nbins
 };
 
-// Code -> bin tables, built on the host by construction (see tables.cpp).
-struct BinTables {
-    uint8_t bin[256];     // uniform-59 bin of a code, or the code itself for 256 bins
-};
-
+// Code -> bin tables, built on the host by construction (tables.cpp).
 void build_uniform59(uint8_t out[256]);
+void build_comparison_luts(const uint8_t bin[256], uint8_t grey[256], uint8_t depth[256]);
+bool fast_path_ok(const FeatParams &fp);
 
 // Kernel launchers (features.hip). All return hipSuccess or the launch error.
 hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &fp,
-                           const uint8_t *d_bin_table, float *hist, uint32_t *counts,
+                           const uint8_t *d_tables, float *hist, uint32_t *counts,
                            hipStream_t s);
 hipError_t launch_debug_codes(const CropDesc *crop, const FeatParams &fp, uint8_t *gcodes,
                               uint8_t *dcodes, uint8_t *mask, int32_t w, int32_t h,
