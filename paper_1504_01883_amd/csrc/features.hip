@@ -255,24 +255,183 @@ __device__ void lbp_hist_generic(const CropDesc &c, const FeatParams &fp, int32_
     }
 }
 
-// Load columns x0..x0+3 of one row: grey bytes packed in G, depth u16 pairs
-// in Z0 (x0, x0+1) and Z1 (x0+2, x0+3). Columns past the crop read column
-// w-1 (their results are never used).
-__device__ __forceinline__ void load_group(const uint8_t *grow, const uint16_t *drow, int x0,
-                                           int w, uint32_t &G, uint32_t &Z0, uint32_t &Z1) {
-    if (x0 + 4 <= w) {
-        G = ld_u32(grow + x0);
-        const uint2 z = ld_u64(drow + x0);
-        Z0 = z.x;
-        Z1 = z.y;
-    } else {
-        const int x1 = min(x0 + 1, w - 1), x2 = min(x0 + 2, w - 1), x3 = min(x0 + 3, w - 1);
-        const int xa = min(x0, w - 1);
-        G = (uint32_t)grow[xa] | ((uint32_t)grow[x1] << 8) | ((uint32_t)grow[x2] << 16) |
-            ((uint32_t)grow[x3] << 24);
-        Z0 = (uint32_t)drow[xa] | ((uint32_t)drow[x1] << 16);
-        Z1 = (uint32_t)drow[x2] | ((uint32_t)drow[x3] << 16);
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Load through the global address space at a 32-bit byte offset from a
+// workgroup-uniform base (global_load with an SGPR base). Unaligned
+// addresses are fine on gfx950.
+template <typename T>
+__device__ __forceinline__ T gld(const void *base, uint32_t byte_off) {
+    typedef __attribute__((address_space(1))) const T gT;
+    return *(const gT *)((const __attribute__((address_space(1))) char *)base + byte_off);
+}
+
+// (a & m) | c with m in an SGPR: one VALU instruction (gfx9 VOP3 takes no
+// literal, so the compiler would otherwise split it into AND + OR).
+__device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t m, uint32_t c) {
+    uint32_t r;
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(m), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+
+// Depth pixels x0..x0+7 of crop row y as four u16 pairs; pixels at x >= w
+// read as 0.
+__device__ __forceinline__ u32x4 depth_chunk(const CropDesc &c, int y, int x0) {
+    if ((c.flags & kCropOverReadOk) || x0 + 8 <= c.w) {
+        u32x4 q = gld<u32x4>(c.depth, ((uint32_t)y * (uint32_t)c.depth_pitch + (uint32_t)x0) * 2u);
+        if (x0 + 8 > c.w) {
+            const int valid = c.w - x0;  // 1..7
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t keep = (2 * i + 1 < valid ? 0xFFFF0000u : 0u) |
+                                      (2 * i < valid ? 0x0000FFFFu : 0u);
+                q[i] &= keep;
+            }
+        }
+        return q;
     }
+    const uint16_t *row = c.depth + (size_t)y * c.depth_pitch;
+    u32x4 q;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t a = (x0 + 2 * i < c.w) ? row[x0 + 2 * i] : 0u;
+        const uint32_t b = (x0 + 2 * i + 1 < c.w) ? row[x0 + 2 * i + 1] : 0u;
+        q[i] = a | (b << 16);
+    }
+    return q;
+}
+
+constexpr int kMedBatch = 8;  // 16-byte chunks in flight per thread
+
+// Ascending bitonic sort of one value per lane across a wave.
+__device__ __forceinline__ uint32_t wave_sort64(uint32_t x, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t y = __shfl_xor(x, j, 64);
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            x = keep_min ? min(x, y) : max(x, y);
+        }
+    }
+    return x;
+}
+
+// Exact lower median of the crop's non-zero depth, -1 if none.
+//  1. Wave 0 estimates it: the lower median of the non-zero values among 64
+//     pixels on an 8 x 8 grid.
+//  2. One pass over the crop: a 1 mm histogram of the 256 values
+//     [lo, lo + 256) around the estimate (LDS atomics on well-spread
+//     addresses), and per-thread counts of the non-zero pixels and of those
+//     below the window (packed 16-bit arithmetic, no atomics).
+//  3. When the median's rank falls inside the window, the window histogram
+//     gives it exactly; otherwise the two-level radix select runs.
+// All threads of the block call it.
+__device__ int32_t crop_median_fast(const CropDesc &c, MedianScratch &ms, uint32_t *sh_red) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < 256; i += kThreads) ms.hist[i] = 0;
+    if (wave == 0) {
+        const int sy = ((2 * (lane >> 3) + 1) * c.h) >> 4;
+        const int sx = ((2 * (lane & 7) + 1) * c.w) >> 4;
+        const uint32_t v = c.depth[(size_t)sy * c.depth_pitch + sx];
+        const uint32_t sorted = wave_sort64(v ? v : 0x10000u, lane);  // zeros last
+        const int nz = __popcll(__ballot(v != 0));
+        const uint32_t est = __shfl(sorted, nz > 0 ? (nz - 1) / 2 : 0, 64);
+        if (lane == 0) ms.rank = nz > 0 ? est : 1000u;
+    }
+    __syncthreads();
+    const int32_t lo = min(max((int32_t)ms.rank - 128, 1), 65536 - 256);
+    const uint32_t lolo = (uint32_t)lo * 0x10001u;
+    const uint32_t lm1 = (uint32_t)(lo - 1) * 0x10001u;
+
+    const int cpr = (c.w + 7) >> 3;
+    const int rows_par = kThreads / cpr;
+    const int cx = tid % cpr, ry0 = tid / cpr;
+    const int nk = ry0 < rows_par ? (c.h - ry0 + rows_par - 1) / rows_par : 0;
+    const int x0 = 8 * cx;
+    uint32_t below2 = 0, nz2 = 0;  // per-half counts
+    for (int kb = 0; kb < nk; kb += kMedBatch) {
+        u32x4 buf[kMedBatch];
+#pragma unroll
+        for (int u = 0; u < kMedBatch; ++u)
+            buf[u] = depth_chunk(c, ry0 + min(kb + u, nk - 1) * rows_par, x0);
+#pragma unroll
+        for (int u = 0; u < kMedBatch; ++u) {
+            if (kb + u >= nk) break;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t q = buf[u][i];
+                // below: 1 <= v < lo, i.e. v - 1 < lo - 1 (v = 0 wraps high).
+                below2 += pk_min(pk_sub_sat(lm1, pk_sub(q, 0x10001u)), 0x10001u);
+                nz2 += pk_min(q, 0x10001u);
+                const uint32_t t = pk_sub(q, lolo);  // v - lo; >= 256 for v = 0
+                const uint32_t t0 = t & 0xFFFFu, t1 = t >> 16;
+                if (t0 < 256u) atomicAdd(&ms.hist[t0], 1u);
+                if (t1 < 256u) atomicAdd(&ms.hist[t1], 1u);
+            }
+        }
+    }
+    const uint32_t below = wave_sum((below2 & 0xFFFFu) + (below2 >> 16));
+    const uint32_t nnz = wave_sum((nz2 & 0xFFFFu) + (nz2 >> 16));
+    if (lane == 0) {
+        sh_red[wave] = below;
+        sh_red[kWaves + wave] = nnz;
+    }
+    __syncthreads();
+    uint32_t tb = 0, tn = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        tb += sh_red[i];
+        tn += sh_red[kWaves + i];
+    }
+    if (tn == 0) return -1;  // uniform: every thread sees the same totals
+    const uint32_t rank = (tn - 1) / 2;
+    if (wave == 0) {
+        if (rank >= tb) {
+            select_bin(ms, rank - tb, lane);  // -1 when the rank lies above the window
+        } else if (lane == 0) {
+            ms.bin = -1;
+        }
+    }
+    __syncthreads();
+    const int32_t bin = ms.bin;
+    __syncthreads();
+    if (bin >= 0) return lo + bin;
+    return crop_median(c, ms);
+}
+
+// Columns x0..x0+3 of one row: grey bytes in G, depth u16 pairs in Z0
+// (x0, x0+1) and Z1 (x0+2, x0+3). With `full` the 4 columns are loaded as is
+// (columns past the crop are never used); otherwise they are clamped to w-1.
+struct RawRow {
+    uint32_t G, Z0, Z1;
+};
+
+__device__ __forceinline__ RawRow load_row(const CropDesc &c, int y, int x0, bool full) {
+    RawRow r;
+    if (full) {
+        r.G = gld<uint32_t>(c.grey, (uint32_t)y * (uint32_t)c.grey_pitch + (uint32_t)x0);
+        const u32x2 z =
+            gld<u32x2>(c.depth, ((uint32_t)y * (uint32_t)c.depth_pitch + (uint32_t)x0) * 2u);
+        r.Z0 = z.x;
+        r.Z1 = z.y;
+    } else {
+        const uint8_t *grow = c.grey + (size_t)y * c.grey_pitch;
+        const uint16_t *drow = c.depth + (size_t)y * c.depth_pitch;
+        const int xa = min(x0, c.w - 1), x1 = min(x0 + 1, c.w - 1), x2 = min(x0 + 2, c.w - 1),
+                  x3 = min(x0 + 3, c.w - 1);
+        r.G = (uint32_t)grow[xa] | ((uint32_t)grow[x1] << 8) | ((uint32_t)grow[x2] << 16) |
+              ((uint32_t)grow[x3] << 24);
+        r.Z0 = (uint32_t)drow[xa] | ((uint32_t)drow[x1] << 16);
+        r.Z1 = (uint32_t)drow[x2] | ((uint32_t)drow[x3] << 16);
+    }
+    return r;
 }
 
 // d' = 0 for d == 0, else clamp(d - lo, 0, span), on a pair of u16.
@@ -285,41 +444,51 @@ __device__ __forceinline__ uint32_t to_window(uint32_t z, int32_t lo, uint32_t l
     return da | (db << 16);
 }
 
-// Row of 6 packed pixels (grey | d' << 16): [x0-1, x0, x0+1, x0+2, x0+3, x0+4].
+// Row of 6 packed pixels (grey | d' << 16): columns [x0-1, x0 .. x0+3, x0+4].
 struct Row6 {
     uint32_t p[6];
 };
 
-__device__ __forceinline__ Row6 make_row(uint32_t G, uint32_t D0, uint32_t D1) {
+__device__ __forceinline__ Row6 make_row(const RawRow &raw, int32_t lo, uint32_t lolo,
+                                         uint32_t span2) {
+    const uint32_t D0 = to_window(raw.Z0, lo, lolo, span2);
+    const uint32_t D1 = to_window(raw.Z1, lo, lolo, span2);
     Row6 r;
-    r.p[1] = __builtin_amdgcn_perm(G, D0, 0x01000C04u);
-    r.p[2] = __builtin_amdgcn_perm(G, D0, 0x03020C05u);
-    r.p[3] = __builtin_amdgcn_perm(G, D1, 0x01000C06u);
-    r.p[4] = __builtin_amdgcn_perm(G, D1, 0x03020C07u);
+    r.p[1] = __builtin_amdgcn_perm(raw.G, D0, 0x01000C04u);
+    r.p[2] = __builtin_amdgcn_perm(raw.G, D0, 0x03020C05u);
+    r.p[3] = __builtin_amdgcn_perm(raw.G, D1, 0x01000C06u);
+    r.p[4] = __builtin_amdgcn_perm(raw.G, D1, 0x03020C07u);
     // Left halo = previous lane's last pixel, right halo = next lane's first.
     r.p[0] = __builtin_amdgcn_update_dpp(0u, r.p[4], 0x138, 0xF, 0xF, false);  // wave_shr:1
     r.p[5] = __builtin_amdgcn_update_dpp(0u, r.p[1], 0x130, 0xF, 0xF, false);  // wave_shl:1
     return r;
 }
 
-// Comparison bits of the centre A/B/C[j] (rows y-1, y, y+1): grey bit of
-// neighbour p at 8+p, depth bit of neighbour p at 25+p (p < 7) and of p7 at
-// 24. A set bit means the neighbour is BELOW the centre.
+// Comparison bits of the centre B[j] against its 8 neighbours in rows A
+// (y-1), B (y), C (y+1): grey bit of neighbour p at 8+p, depth bit of
+// neighbour p at 25+p (p < 7) and of p7 at 24. A set bit means the
+// neighbour is BELOW the centre. For a negative 16-bit difference every bit
+// from 8 (grey, |diff| < 256) or 9 (depth, |diff| < 512) up is set.
 __device__ __forceinline__ uint32_t compare_bits(const Row6 &A, const Row6 &B, const Row6 &C, int j) {
     const uint32_t c = B.p[j];
+    // All eight differences first: a packed result read by the very next
+    // instruction costs a wait state on gfx950.
     const uint32_t d0 = pk_sub(A.p[j - 1], c), d1 = pk_sub(A.p[j], c), d2 = pk_sub(A.p[j + 1], c);
     const uint32_t d3 = pk_sub(B.p[j + 1], c), d4 = pk_sub(C.p[j + 1], c), d5 = pk_sub(C.p[j], c);
     const uint32_t d6 = pk_sub(C.p[j - 1], c), d7 = pk_sub(B.p[j - 1], c);
-    uint32_t acc = (d0 & 0x02000100u) | (d1 & 0x04000200u);
-    acc |= d2 & 0x08000400u;
-    acc |= d3 & 0x10000800u;
-    acc |= d4 & 0x20001000u;
-    acc |= d5 & 0x40002000u;
-    acc |= d6 & 0x80004000u;
-    acc |= d7 & 0x00008000u;
-    acc |= (d7 >> 7) & 0x01000000u;
+    uint32_t acc = d0 & 0x02000100u;
+    acc = and_or(d1, 0x04000200u, acc);
+    acc = and_or(d2, 0x08000400u, acc);
+    acc = and_or(d3, 0x10000800u, acc);
+    acc = and_or(d4, 0x20001000u, acc);
+    acc = and_or(d5, 0x40002000u, acc);
+    acc = and_or(d6, 0x80004000u, acc);
+    acc = and_or(d7, 0x00008000u, acc);
+    acc = and_or(d7 >> 7, 0x01000000u, acc);
     return acc;
 }
+
+constexpr int kRowPrefetch = 4;
 
 __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__restrict__ crops,
                                                             FeatParams fp,
@@ -335,10 +504,11 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
     __shared__ uint8_t sh_rowband[LBPF_MAX_SIDE];
     __shared__ uint8_t sh_colband[LBPF_MAX_SIDE];
     __shared__ float sh_q[kQuot];
-    __shared__ uint32_t sh_red[kWaves];
+    __shared__ uint32_t sh_red[2 * kWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const CropDesc c = crops[blockIdx.x];
+    const int w = c.w, h = c.h;
     const int gx = fp.grid_x, gy = fp.grid_y, cells = gx * gy;
     const int dim = fp.dim;
 
@@ -349,66 +519,72 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
         sh_lut_d[i] = tables[512 + i];
     }
     // Coordinate y lies in band floor(((y + 1) g - 1) / n) of a side of length n.
-    for (int y = tid; y < c.h; y += kThreads) sh_rowband[y] = (uint8_t)(((y + 1) * gy - 1) / c.h);
-    for (int x = tid; x < c.w; x += kThreads) sh_colband[x] = (uint8_t)(((x + 1) * gx - 1) / c.w);
+    for (int y = tid; y < h; y += kThreads) sh_rowband[y] = (uint8_t)(((y + 1) * gy - 1) / h);
+    for (int x = tid; x < w; x += kThreads) sh_colband[x] = (uint8_t)(((x + 1) * gx - 1) / w);
 
-    const int32_t m = crop_median(c, ms);  // ends with a barrier
+    const int32_t m = crop_median_fast(c, ms, sh_red);  // ends with a barrier
 
-    if (c.w <= kFastMaxW) {
+    if (w <= kFastMaxW) {
         if (m >= 0) {
-            const int L = (c.w + 3) >> 2;         // lanes per stream (<= 64)
+            const int L = (w + 3) >> 2;           // lanes per stream (<= 64)
             const int spw = 64 / L;               // streams per wave
             const int sw = lane / L;              // stream of this lane within the wave
             const int x0 = 4 * (lane - sw * L);
             const int S = kWaves * spw;
             const int s = wave * spw + (sw < spw ? sw : 0);
-            const int rows = c.h - 2;
+            const int rows = h - 2;
             const int yb = 1 + (s * rows) / S;
             const int ye = (sw < spw) ? 1 + ((s + 1) * rows) / S : yb;
+            const bool full = (c.flags & kCropOverReadOk) || x0 + 4 <= w;
 
             const int32_t lo = m - fp.window;
             const uint32_t lolo = (uint32_t)(lo & 0xFFFF) * 0x10001u;
             const uint32_t span2 = (uint32_t)(2 * fp.window) * 0x10001u;
             const uint32_t in_hi = (uint32_t)(2 * fp.window - 1) << 16;
 
-            // Column part of each pixel's histogram index, and the discard slot.
-            int colpart[4];
+            // Per column: histogram column offset (bytes) and in-window
+            // threshold (0 for border or out-of-crop columns: never counted).
+            uint32_t col4[4], thr[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) colpart[k] = sh_colband[min(x0 + k, c.w - 1)] * kU59;
-            const int discard = dim + lane;
-            const int dep_off = cells * kU59;
-
-            const uint8_t *gbase = c.grey;
-            const uint16_t *dbase = c.depth;
-            Row6 A, B, C;
-            if (yb < ye) {
-                uint32_t G, Z0, Z1;
-                load_group(gbase + (size_t)(yb - 1) * c.grey_pitch,
-                           dbase + (size_t)(yb - 1) * c.depth_pitch, x0, c.w, G, Z0, Z1);
-                A = make_row(G, to_window(Z0, lo, lolo, span2), to_window(Z1, lo, lolo, span2));
-                load_group(gbase + (size_t)yb * c.grey_pitch, dbase + (size_t)yb * c.depth_pitch,
-                           x0, c.w, G, Z0, Z1);
-                B = make_row(G, to_window(Z0, lo, lolo, span2), to_window(Z1, lo, lolo, span2));
+            for (int k = 0; k < 4; ++k) {
+                const int x = x0 + k;
+                col4[k] = (uint32_t)(sh_colband[min(x, w - 1)] * kU59) * 4u;
+                thr[k] = (x >= 1 && x <= w - 2) ? in_hi : 0u;
             }
-            for (int y = yb; y < ye; ++y) {
-                uint32_t G, Z0, Z1;
-                load_group(gbase + (size_t)(y + 1) * c.grey_pitch,
-                           dbase + (size_t)(y + 1) * c.depth_pitch, x0, c.w, G, Z0, Z1);
-                C = make_row(G, to_window(Z0, lo, lolo, span2), to_window(Z1, lo, lolo, span2));
-                const int rowpart = sh_rowband[y] * gx * kU59;
+            const uint32_t dep4 = (uint32_t)(cells * kU59) * 4u;
+            char *hbase = reinterpret_cast<char *>(sh_hist);
+
+            Row6 A, B;
+            if (yb < ye) {
+                A = make_row(load_row(c, yb - 1, x0, full), lo, lolo, span2);
+                B = make_row(load_row(c, yb, x0, full), lo, lolo, span2);
+            }
+            RawRow ring[kRowPrefetch];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t bits = compare_bits(A, B, C, k + 1);
-                    const int x = x0 + k;
-                    const bool in = (B.p[k + 1] - 0x10000u) < in_hi && x >= 1 && x <= c.w - 2;
-                    const int base = rowpart + colpart[k];
-                    const int ig = in ? base + sh_lut_g[(bits >> 8) & 0xFFu] : discard;
-                    const int id = in ? dep_off + base + sh_lut_d[bits >> 24] : discard;
-                    atomicAdd(&sh_hist[ig], 1u);
-                    atomicAdd(&sh_hist[id], 1u);
+            for (int u = 0; u < kRowPrefetch; ++u) ring[u] = load_row(c, min(yb + 1 + u, h - 1), x0, full);
+
+            for (int y = yb; y < ye; y += kRowPrefetch) {
+#pragma unroll
+                for (int u = 0; u < kRowPrefetch; ++u) {
+                    const int yy = y + u;
+                    if (yy >= ye) break;
+                    const Row6 C = make_row(ring[u], lo, lolo, span2);
+                    ring[u] = load_row(c, min(yy + 1 + kRowPrefetch, h - 1), x0, full);
+                    const uint32_t row4 = (uint32_t)(sh_rowband[yy] * gx * kU59) * 4u;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t bits = compare_bits(A, B, C, k + 1);
+                        if (B.p[k + 1] - 0x10000u < thr[k]) {
+                            const uint32_t base = row4 + col4[k];
+                            const uint32_t bg = sh_lut_g[(bits >> 8) & 0xFFu];
+                            const uint32_t bd = sh_lut_d[bits >> 24];
+                            atomicAdd(reinterpret_cast<uint32_t *>(hbase + base + 4u * bg), 1u);
+                            atomicAdd(reinterpret_cast<uint32_t *>(hbase + dep4 + base + 4u * bd), 1u);
+                        }
+                    }
+                    A = B;
+                    B = C;
                 }
-                A = B;
-                B = C;
             }
         }
     } else {
@@ -424,9 +600,9 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
     __syncthreads();
     uint32_t n_in = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) n_in += sh_red[w];
+    for (int i = 0; i < kWaves; ++i) n_in += sh_red[i];
     const float T = (float)(2u * n_in);
-    const int maxc = ((c.h + gy - 1) / gy) * ((c.w + gx - 1) / gx);  // cell capacity bound
+    const int maxc = ((h + gy - 1) / gy) * ((w + gx - 1) / gx);  // cell capacity bound
     const bool tab = maxc < kQuot;
     if (tab) {
         for (int v = tid; v <= maxc; v += kThreads) sh_q[v] = n_in ? (float)v / T : 0.0f;

@@ -10,14 +10,20 @@
 namespace lbpf {
 
 // One face crop, resolved on the host from (image, box): plane pointers at
-// the crop origin, pitches in elements, size. 32 bytes, read once per
+// the crop origin, pitches in elements, size, flags. 32 bytes, read once per
 // workgroup.
 struct CropDesc {
     const uint8_t *grey;
     const uint16_t *depth;
     int32_t grey_pitch, depth_pitch;
-    int32_t w, h;
+    int16_t w, h;
+    uint32_t flags;
 };
+// Every row of the crop may be read up to kOverRead elements past its right
+// edge in both planes without leaving the image (the bytes read there are
+// never used).
+constexpr uint32_t kCropOverReadOk = 1u;
+constexpr int kOverRead = 7;
 static_assert(sizeof(CropDesc) == 32, "CropDesc layout");
 
 // Feature geometry shared by every kernel launch of a context.

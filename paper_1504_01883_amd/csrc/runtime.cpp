@@ -113,8 +113,16 @@ lbpf_status resolve(const lbpf_ctx *ctx, const lbpf_image *images, int32_t n_ima
         c.depth = im.depth + (size_t)b.y * im.depth_pitch + b.x;
         c.grey_pitch = im.grey_pitch;
         c.depth_pitch = im.depth_pitch;
-        c.w = b.w;
-        c.h = b.h;
+        c.w = (int16_t)b.w;
+        c.h = (int16_t)b.h;
+        // An image spans at least (height - 1) * pitch + width elements; the
+        // furthest over-read is kOverRead past the crop's last row.
+        const int64_t last = (int64_t)(b.y + b.h - 1);
+        const bool g_ok = !im.grey || last * im.grey_pitch + b.x + b.w + kOverRead <=
+                                          (int64_t)(im.height - 1) * im.grey_pitch + im.width;
+        const bool d_ok = last * im.depth_pitch + b.x + b.w + kOverRead <=
+                          (int64_t)(im.height - 1) * im.depth_pitch + im.width;
+        c.flags = (g_ok && d_ok) ? kCropOverReadOk : 0u;
     }
     return LBPF_OK;
 }

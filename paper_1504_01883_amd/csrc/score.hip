@@ -40,27 +40,28 @@ __device__ __forceinline__ floatx4 load_frag(const float *__restrict__ base, int
     return v;
 }
 
-// A workgroup of 4 wave64 owns a 64 x 64 tile of S. Wave w computes rows
-// 32 (w & 1) .. +32 of the tile over one half of the feature dimension
-// (w >> 1), as 2 x 4 blocks of 16 x 16; the two halves are summed through
-// LDS at the end. Each iteration covers 32 feature columns (2 sub-steps of
+// A workgroup of 8 wave64 owns a 64 x 64 tile of S. Wave w computes rows
+// 32 (w & 1) .. +32 of the tile over one quarter of the feature dimension
+// (w >> 1), as 2 x 4 blocks of 16 x 16; the quarters are summed in a fixed
+// order through LDS at the end. Two waves per SIMD hide each other's load
+// latency. Each iteration covers 32 feature columns (2 sub-steps of
 // 16) and the operands of the next iteration are loaded before the MFMAs of
 // the current one are issued, so a global load has a full iteration of MFMA
 // work (64 instructions) to land.
 template <bool kVec>
-__global__ __launch_bounds__(256) void k_score_f32(const float *__restrict__ X, int32_t N,
+__global__ __launch_bounds__(512) void k_score_f32(const float *__restrict__ X, int32_t N,
                                                    const float *__restrict__ W,
                                                    const float *__restrict__ bias, int32_t K,
                                                    int32_t D, float *__restrict__ S) {
-    __shared__ floatx4 partial[2][2][4][64];  // [row half][i][j][lane]
+    __shared__ floatx4 partial[3][2][2][4][64];  // [quarter-1][row half][i][j][lane]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const int rh = wave & 1, kh = wave >> 1;
+    const int rh = wave & 1, kq = wave >> 1;
     const int32_t n0 = blockIdx.x * kTile + rh * 32;
     const int32_t k0 = blockIdx.y * kTile;
-    const int32_t dh = ((D + 63) / 64) * 32;  // first half: [0, dh), multiple of 32
-    const int32_t d_begin = kh ? dh : 0;
-    const int32_t d_end = kh ? D : (dh < D ? dh : D);
+    const int32_t dq = ((D + 127) / 128) * 32;  // quarter length, a multiple of 32
+    const int32_t d_begin = min(kq * dq, D);
+    const int32_t d_end = min(d_begin + dq, D);
 
     floatx4 acc[2][4];
 #pragma unroll
@@ -103,15 +104,15 @@ __global__ __launch_bounds__(256) void k_score_f32(const float *__restrict__ X, 
         }
     }
 
-    // Second-half waves hand their sums to the first-half wave of the same rows.
-    if (kh == 1) {
+    // Waves of quarters 1..3 hand their sums to the quarter-0 wave of the same rows.
+    if (kq > 0) {
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) partial[rh][i][j][lane] = acc[i][j];
+            for (int j = 0; j < 4; ++j) partial[kq - 1][rh][i][j][lane] = acc[i][j];
     }
     __syncthreads();
-    if (kh == 1) return;
+    if (kq > 0) return;
     // Lane l holds S[n0 + 16 i + 4 q + t][k0 + 16 j + r] in acc[i][j][t].
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -120,11 +121,12 @@ __global__ __launch_bounds__(256) void k_score_f32(const float *__restrict__ X, 
         const float bk = bias[k];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const floatx4 o = partial[rh][i][j][lane];
+            const floatx4 s = ((acc[i][j] + partial[0][rh][i][j][lane]) +
+                               partial[1][rh][i][j][lane]) + partial[2][rh][i][j][lane];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int32_t n = n0 + 16 * i + 4 * q + t;
-                if (n < N) S[(size_t)n * K + k] = (acc[i][j][t] + o[t]) + bk;
+                if (n < N) S[(size_t)n * K + k] = s[t] + bk;
             }
         }
     }
@@ -168,9 +170,9 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
     dim3 grid((N + kTile - 1) / kTile, (K + kTile - 1) / kTile);
     const bool vec = (D % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
     if (vec)
-        hipLaunchKernelGGL(k_score_f32<true>, grid, dim3(256), 0, s, X, N, W, b, K, D, S);
+        hipLaunchKernelGGL(k_score_f32<true>, grid, dim3(512), 0, s, X, N, W, b, K, D, S);
     else
-        hipLaunchKernelGGL(k_score_f32<false>, grid, dim3(256), 0, s, X, N, W, b, K, D, S);
+        hipLaunchKernelGGL(k_score_f32<false>, grid, dim3(512), 0, s, X, N, W, b, K, D, S);
     return hipGetLastError();
 }
 
