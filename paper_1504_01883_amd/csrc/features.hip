@@ -335,6 +335,17 @@ __device__ __forceinline__ uint32_t wave_sort64(uint32_t x, int lane) {
 // All threads of the block call it.
 __device__ int32_t crop_median_fast(const CropDesc &c, MedianScratch &ms, uint32_t *sh_red) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cpr = (c.w + 7) >> 3;
+    const int rows_par = kThreads / cpr;
+    const int cx = tid % cpr, ry0 = tid / cpr;
+    const int nk = ry0 < rows_par ? (c.h - ry0 + rows_par - 1) / rows_par : 0;
+    const int x0 = 8 * cx;
+    // The first batch of chunks does not depend on the estimate: issue its
+    // loads before the estimate is taken so the two latencies overlap.
+    u32x4 buf[kMedBatch];
+#pragma unroll
+    for (int u = 0; u < kMedBatch; ++u)
+        if (nk > 0) buf[u] = depth_chunk(c, ry0 + min(u, nk - 1) * rows_par, x0);
     for (int i = tid; i < 256; i += kThreads) ms.hist[i] = 0;
     if (wave == 0) {
         const int sy = ((2 * (lane >> 3) + 1) * c.h) >> 4;
@@ -350,17 +361,13 @@ __device__ int32_t crop_median_fast(const CropDesc &c, MedianScratch &ms, uint32
     const uint32_t lolo = (uint32_t)lo * 0x10001u;
     const uint32_t lm1 = (uint32_t)(lo - 1) * 0x10001u;
 
-    const int cpr = (c.w + 7) >> 3;
-    const int rows_par = kThreads / cpr;
-    const int cx = tid % cpr, ry0 = tid / cpr;
-    const int nk = ry0 < rows_par ? (c.h - ry0 + rows_par - 1) / rows_par : 0;
-    const int x0 = 8 * cx;
     uint32_t below2 = 0, nz2 = 0;  // per-half counts
     for (int kb = 0; kb < nk; kb += kMedBatch) {
-        u32x4 buf[kMedBatch];
+        if (kb > 0) {
 #pragma unroll
-        for (int u = 0; u < kMedBatch; ++u)
-            buf[u] = depth_chunk(c, ry0 + min(kb + u, nk - 1) * rows_par, x0);
+            for (int u = 0; u < kMedBatch; ++u)
+                buf[u] = depth_chunk(c, ry0 + min(kb + u, nk - 1) * rows_par, x0);
+        }
 #pragma unroll
         for (int u = 0; u < kMedBatch; ++u) {
             if (kb + u >= nk) break;
@@ -496,7 +503,7 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
                                                             float *__restrict__ hist,
                                                             uint32_t *__restrict__ counts) {
     // fp.dim = 2 * cells * 59 counters, then 64 per-lane discard slots.
-    __shared__ uint32_t sh_hist[2 * 64 * kU59 + 64];
+    __shared__ __attribute__((aligned(16))) uint32_t sh_hist[2 * 64 * kU59 + 64];
     __shared__ MedianScratch ms;
     __shared__ uint8_t sh_bin[256];      // code -> bin
     __shared__ uint8_t sh_lut_g[256];    // grey comparison byte -> bin
@@ -610,10 +617,21 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
     }
     float *out = hist + (size_t)blockIdx.x * dim;
     uint32_t *cout = counts ? counts + (size_t)blockIdx.x * dim : nullptr;
-    for (int i = tid; i < dim; i += kThreads) {
-        const uint32_t v = sh_hist[i];
-        out[i] = tab ? sh_q[v] : (n_in ? (float)v / T : 0.0f);
-        if (cout) cout[i] = v;
+    const bool vec = (dim & 3) == 0 && ((uintptr_t)out & 15) == 0 && ((uintptr_t)cout & 15) == 0;
+    if (vec && tab) {
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        for (int i = 4 * tid; i < dim; i += 4 * kThreads) {
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(&sh_hist[i]);
+            const f32x4 f = {sh_q[v.x], sh_q[v.y], sh_q[v.z], sh_q[v.w]};
+            *reinterpret_cast<f32x4 *>(out + i) = f;
+            if (cout) *reinterpret_cast<u32x4 *>(cout + i) = v;
+        }
+    } else {
+        for (int i = tid; i < dim; i += kThreads) {
+            const uint32_t v = sh_hist[i];
+            out[i] = tab ? sh_q[v] : (n_in ? (float)v / T : 0.0f);
+            if (cout) cout[i] = v;
+        }
     }
 }
 
