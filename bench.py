@@ -43,8 +43,10 @@ def _parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=1024,
+    p.add_argument("--cpu-sample", type=int, default=4096,
                    help="crops of the workload the CPU oracle is timed on")
+    p.add_argument("--plain-sample", type=int, default=512,
+                   help="crops the plain unbatched GPU path is timed on")
     return p.parse_args()
 
 
@@ -168,6 +170,8 @@ def main():
                 "peak": dk["peak"], "unit": dk["unit"], "frac": dk["frac"],
                 "traffic": dk["traffic"]}
 
+    plain = plain_path(ctx, planes[0], wts, args.plain_sample, ms_step)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(grey, depth, W, b, argmax.cpu().numpy(), args.cpu_sample)
@@ -192,6 +196,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "kernels": kernels,
+        "plain_gpu_path": plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -199,6 +204,31 @@ def main():
         bt.close()
     wts.close()
     ctx.close()
+
+
+def plain_path(ctx, plane, wts, sample, fused_ms_step):
+    """The plain unbatched FP32 GPU path (per-crop launches, global atomics,
+    GEMV scoring) on the first `sample` crops of the same resident inputs."""
+    import torch
+    from paper_1504_01883_amd import synth
+    n = min(sample, N_CROPS)
+    boxes = synth.stacked_boxes(n, SIDE, SIDE)
+    hist = torch.empty((n, 2 * GRID * GRID * 59), dtype=torch.float32, device="cuda")
+    S = torch.empty((n, N_IDENT), dtype=torch.float32, device="cuda")
+    A = torch.empty((n,), dtype=torch.int32, device="cuda")
+    ctx.features_plain([plane], boxes[:8], out=hist[:8])
+    ctx.score_plain(hist[:8], wts, scores_out=S[:8], argmax_out=A[:8])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.features_plain([plane], boxes, out=hist)
+    ctx.score_plain(hist, wts, scores_out=S, argmax_out=A)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = n / (e0.elapsed_time(e1) * 1e-3)
+    fused = N_CROPS / (fused_ms_step * 1e-3)
+    return {"value": rate, "unit": "crops/s", "sample": f"first {n} crops, one crop per launch",
+            "fused_speedup": fused / rate}
 
 
 def cpu_baseline(grey, depth, W, b, gpu_argmax, sample):

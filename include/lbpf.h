@@ -156,6 +156,43 @@ int32_t lbpf_batch_size(const lbpf_batch *batch);
 lbpf_status lbpf_features_batch(lbpf_ctx *ctx, const lbpf_batch *batch, float *hist,
                                 uint32_t *counts_opt, void *stream);
 
+/* Launch shape of the fused feature kernel for one batch. persistent = 0:
+ * one workgroup per crop; 1: wg_per_cu workgroups per compute unit take
+ * crops from a device work queue (sorted = 1: largest crop first) until it is
+ * empty. row_prefetch (2 or 4) is how many rows ahead each lane loads. The
+ * outputs do not depend on the launch shape. */
+typedef struct lbpf_launch_cfg {
+    int32_t persistent;
+    int32_t wg_per_cu;
+    int32_t row_prefetch;
+    int32_t sorted;
+} lbpf_launch_cfg;
+
+/* Set / read a batch's launch shape (default {0, 4, 4, 1}). LBPF_E_INVALID
+ * for values outside the ranges above. */
+lbpf_status lbpf_batch_set_launch(lbpf_batch *batch, const lbpf_launch_cfg *cfg);
+lbpf_status lbpf_batch_get_launch(const lbpf_batch *batch, lbpf_launch_cfg *cfg);
+
+/* Autotuner: time every candidate launch shape on this batch (reps timed
+ * launches each, HIP events on `stream`, synchronous), keep the fastest in
+ * the batch and report it (best_out, best_us_out may be NULL). hist is a
+ * DEVICE [n][D] FP32 scratch the runs write into. */
+lbpf_status lbpf_tune_batch(lbpf_ctx *ctx, lbpf_batch *batch, float *hist, int32_t reps,
+                            lbpf_launch_cfg *best_out, float *best_us_out, void *stream);
+
+/* Capture features (+ optionally scores/argmax) of a batch into a HIP graph
+ * and instantiate it; replays recompute everything from the batch's current
+ * input planes. weights NULL captures the features only. hist, scores_opt,
+ * argmax_opt are DEVICE outputs as for lbpf_features_batch / lbpf_score; the
+ * caller keeps them alive. The graph holds no memset nodes: the persistent
+ * kernel's work queue resets itself, so replays need nothing in between. */
+typedef struct lbpf_graph lbpf_graph;
+lbpf_status lbpf_graph_create(lbpf_ctx *ctx, const lbpf_batch *batch,
+                              const lbpf_weights *weights, float *hist, float *scores_opt,
+                              int32_t *argmax_opt, lbpf_graph **out);
+lbpf_status lbpf_graph_launch(lbpf_graph *graph, void *stream);
+void lbpf_graph_destroy(lbpf_graph *graph);
+
 /* Enrol K identities: W DEVICE [K][D] FP32 row-major, b DEVICE [K] FP32.
  * The library copies them (and, for BF16/FP16/FP8, quantises them) into a
  * weights object it owns; the caller's buffers may be freed once `stream`
@@ -175,6 +212,24 @@ int32_t lbpf_weights_count(const lbpf_weights *weights);
  * the products accumulated in FP32. Errors: LBPF_E_INVALID, LBPF_E_HIP. */
 lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_weights *weights,
                        float *scores_opt, int32_t *argmax_opt, void *stream);
+
+/* The plain unbatched FP32 GPU path, kept as the comparator of the fused
+ * path: the same outputs, computed the straightforward way one crop at a
+ * time (Sec. 3 extracts features face by face): per crop a median kernel, a
+ * one-thread-per-pixel LBP kernel incrementing the crop's histogram with
+ * global-memory atomics, and a normalisation kernel. Same arguments, results
+ * (bit-exact) and errors as lbpf_features; counts_opt NULL uses a context
+ * scratch row. Crops run in order on `stream`. */
+lbpf_status lbpf_features_plain(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                                const lbpf_box *boxes, int32_t n_boxes, float *hist,
+                                uint32_t *counts_opt, void *stream);
+
+/* Plain scoring: one GEMV kernel (one thread per identity, FP32 fused
+ * multiply-adds) and one argmax kernel per feature row. Same arguments as
+ * lbpf_score; FP32 weights only (LBPF_E_UNSUPPORTED otherwise). */
+lbpf_status lbpf_score_plain(lbpf_ctx *ctx, const float *hist, int32_t N,
+                             const lbpf_weights *weights, float *scores_opt,
+                             int32_t *argmax_opt, void *stream);
 
 /* Test hook: per-pixel codes and mask of ONE box, for bit-exact checks.
  * image/box are HOST structs; grey_codes, depth_codes, mask are DEVICE

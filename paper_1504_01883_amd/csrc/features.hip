@@ -43,6 +43,8 @@
 //     cell can hold, then the row is written by table lookup.
 #include "lbpf_internal.h"
 
+#include <algorithm>
+
 namespace lbpf {
 
 namespace {
@@ -495,41 +497,46 @@ __device__ __forceinline__ uint32_t compare_bits(const Row6 &A, const Row6 &B, c
     return acc;
 }
 
-constexpr int kRowPrefetch = 4;
-
-__global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__restrict__ crops,
-                                                            FeatParams fp,
-                                                            const uint8_t *__restrict__ tables,
-                                                            float *__restrict__ hist,
-                                                            uint32_t *__restrict__ counts) {
+// LDS of the fast path; 38.7 KB, so four workgroups fit a CU.
+struct FastShared {
     // fp.dim = 2 * cells * 59 counters, then 64 per-lane discard slots.
-    __shared__ __attribute__((aligned(16))) uint32_t sh_hist[2 * 64 * kU59 + 64];
-    __shared__ MedianScratch ms;
-    __shared__ uint8_t sh_bin[256];      // code -> bin
-    __shared__ uint8_t sh_lut_g[256];    // grey comparison byte -> bin
-    __shared__ uint8_t sh_lut_d[256];    // depth comparison byte -> bin
-    __shared__ uint8_t sh_rowband[LBPF_MAX_SIDE];
-    __shared__ uint8_t sh_colband[LBPF_MAX_SIDE];
-    __shared__ float sh_q[kQuot];
-    __shared__ uint32_t sh_red[2 * kWaves];
+    __attribute__((aligned(16))) uint32_t hist[2 * 64 * kU59 + 64];
+    MedianScratch ms;
+    uint8_t bin[256];    // code -> bin
+    uint8_t lut_g[256];  // grey comparison byte -> bin
+    uint8_t lut_d[256];  // depth comparison byte -> bin
+    uint8_t rowband[LBPF_MAX_SIDE];
+    uint8_t colband[LBPF_MAX_SIDE];
+    float q[kQuot];
+    uint32_t red[2 * kWaves];
+    int32_t next;
+};
 
+__device__ __forceinline__ void load_tables(FastShared &sh, const uint8_t *tables) {
+    for (int i = threadIdx.x; i < 256; i += kThreads) {
+        sh.bin[i] = tables[i];
+        sh.lut_g[i] = tables[256 + i];
+        sh.lut_d[i] = tables[512 + i];
+    }
+}
+
+// Features of one crop by the whole workgroup: row `out` (and `cout` when
+// not null) of length fp.dim. The tables must already be in LDS; the caller
+// separates consecutive crops with a barrier. kPF = rows loaded ahead.
+template <int kPF>
+__device__ void fast_crop(const CropDesc &c, const FeatParams &fp, FastShared &sh, float *out,
+                          uint32_t *cout) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const CropDesc c = crops[blockIdx.x];
     const int w = c.w, h = c.h;
     const int gx = fp.grid_x, gy = fp.grid_y, cells = gx * gy;
     const int dim = fp.dim;
 
-    for (int i = tid; i < dim + 64; i += kThreads) sh_hist[i] = 0;
-    for (int i = tid; i < 256; i += kThreads) {
-        sh_bin[i] = tables[i];
-        sh_lut_g[i] = tables[256 + i];
-        sh_lut_d[i] = tables[512 + i];
-    }
+    for (int i = tid; i < dim + 64; i += kThreads) sh.hist[i] = 0;
     // Coordinate y lies in band floor(((y + 1) g - 1) / n) of a side of length n.
-    for (int y = tid; y < h; y += kThreads) sh_rowband[y] = (uint8_t)(((y + 1) * gy - 1) / h);
-    for (int x = tid; x < w; x += kThreads) sh_colband[x] = (uint8_t)(((x + 1) * gx - 1) / w);
+    for (int y = tid; y < h; y += kThreads) sh.rowband[y] = (uint8_t)(((y + 1) * gy - 1) / h);
+    for (int x = tid; x < w; x += kThreads) sh.colband[x] = (uint8_t)(((x + 1) * gx - 1) / w);
 
-    const int32_t m = crop_median_fast(c, ms, sh_red);  // ends with a barrier
+    const int32_t m = crop_median_fast(c, sh.ms, sh.red);  // ends with a barrier
 
     if (w <= kFastMaxW) {
         if (m >= 0) {
@@ -555,36 +562,36 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int x = x0 + k;
-                col4[k] = (uint32_t)(sh_colband[min(x, w - 1)] * kU59) * 4u;
+                col4[k] = (uint32_t)(sh.colband[min(x, w - 1)] * kU59) * 4u;
                 thr[k] = (x >= 1 && x <= w - 2) ? in_hi : 0u;
             }
             const uint32_t dep4 = (uint32_t)(cells * kU59) * 4u;
-            char *hbase = reinterpret_cast<char *>(sh_hist);
+            char *hbase = reinterpret_cast<char *>(sh.hist);
 
             Row6 A, B;
             if (yb < ye) {
                 A = make_row(load_row(c, yb - 1, x0, full), lo, lolo, span2);
                 B = make_row(load_row(c, yb, x0, full), lo, lolo, span2);
             }
-            RawRow ring[kRowPrefetch];
+            RawRow ring[kPF];
 #pragma unroll
-            for (int u = 0; u < kRowPrefetch; ++u) ring[u] = load_row(c, min(yb + 1 + u, h - 1), x0, full);
+            for (int u = 0; u < kPF; ++u) ring[u] = load_row(c, min(yb + 1 + u, h - 1), x0, full);
 
-            for (int y = yb; y < ye; y += kRowPrefetch) {
+            for (int y = yb; y < ye; y += kPF) {
 #pragma unroll
-                for (int u = 0; u < kRowPrefetch; ++u) {
+                for (int u = 0; u < kPF; ++u) {
                     const int yy = y + u;
                     if (yy >= ye) break;
                     const Row6 C = make_row(ring[u], lo, lolo, span2);
-                    ring[u] = load_row(c, min(yy + 1 + kRowPrefetch, h - 1), x0, full);
-                    const uint32_t row4 = (uint32_t)(sh_rowband[yy] * gx * kU59) * 4u;
+                    ring[u] = load_row(c, min(yy + 1 + kPF, h - 1), x0, full);
+                    const uint32_t row4 = (uint32_t)(sh.rowband[yy] * gx * kU59) * 4u;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const uint32_t bits = compare_bits(A, B, C, k + 1);
                         if (B.p[k + 1] - 0x10000u < thr[k]) {
                             const uint32_t base = row4 + col4[k];
-                            const uint32_t bg = sh_lut_g[(bits >> 8) & 0xFFu];
-                            const uint32_t bd = sh_lut_d[bits >> 24];
+                            const uint32_t bg = sh.lut_g[(bits >> 8) & 0xFFu];
+                            const uint32_t bd = sh.lut_d[bits >> 24];
                             atomicAdd(reinterpret_cast<uint32_t *>(hbase + base + 4u * bg), 1u);
                             atomicAdd(reinterpret_cast<uint32_t *>(hbase + dep4 + base + 4u * bd), 1u);
                         }
@@ -595,42 +602,83 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
             }
         }
     } else {
-        lbp_hist_generic(c, fp, m, sh_bin, sh_rowband, sh_colband, sh_hist);
+        lbp_hist_generic(c, fp, m, sh.bin, sh.rowband, sh.colband, sh.hist);
     }
     __syncthreads();
 
     // n_in = total of the grey half; T = 2 n_in.
     uint32_t part = 0;
-    for (int i = tid; i < cells * kU59; i += kThreads) part += sh_hist[i];
+    for (int i = tid; i < cells * kU59; i += kThreads) part += sh.hist[i];
     part = wave_sum(part);
-    if (lane == 0) sh_red[wave] = part;
+    if (lane == 0) sh.red[wave] = part;
     __syncthreads();
     uint32_t n_in = 0;
 #pragma unroll
-    for (int i = 0; i < kWaves; ++i) n_in += sh_red[i];
+    for (int i = 0; i < kWaves; ++i) n_in += sh.red[i];
     const float T = (float)(2u * n_in);
     const int maxc = ((h + gy - 1) / gy) * ((w + gx - 1) / gx);  // cell capacity bound
     const bool tab = maxc < kQuot;
     if (tab) {
-        for (int v = tid; v <= maxc; v += kThreads) sh_q[v] = n_in ? (float)v / T : 0.0f;
+        for (int v = tid; v <= maxc; v += kThreads) sh.q[v] = n_in ? (float)v / T : 0.0f;
         __syncthreads();
     }
-    float *out = hist + (size_t)blockIdx.x * dim;
-    uint32_t *cout = counts ? counts + (size_t)blockIdx.x * dim : nullptr;
     const bool vec = (dim & 3) == 0 && ((uintptr_t)out & 15) == 0 && ((uintptr_t)cout & 15) == 0;
     if (vec && tab) {
         typedef float f32x4 __attribute__((ext_vector_type(4)));
         for (int i = 4 * tid; i < dim; i += 4 * kThreads) {
-            const u32x4 v = *reinterpret_cast<const u32x4 *>(&sh_hist[i]);
-            const f32x4 f = {sh_q[v.x], sh_q[v.y], sh_q[v.z], sh_q[v.w]};
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(&sh.hist[i]);
+            const f32x4 f = {sh.q[v.x], sh.q[v.y], sh.q[v.z], sh.q[v.w]};
             *reinterpret_cast<f32x4 *>(out + i) = f;
             if (cout) *reinterpret_cast<u32x4 *>(cout + i) = v;
         }
     } else {
         for (int i = tid; i < dim; i += kThreads) {
-            const uint32_t v = sh_hist[i];
-            out[i] = tab ? sh_q[v] : (n_in ? (float)v / T : 0.0f);
+            const uint32_t v = sh.hist[i];
+            out[i] = tab ? sh.q[v] : (n_in ? (float)v / T : 0.0f);
             if (cout) cout[i] = v;
+        }
+    }
+}
+
+// One workgroup per crop.
+template <int kPF>
+__global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__restrict__ crops,
+                                                            FeatParams fp,
+                                                            const uint8_t *__restrict__ tables,
+                                                            float *__restrict__ hist,
+                                                            uint32_t *__restrict__ counts) {
+    __shared__ FastShared sh;
+    load_tables(sh, tables);
+    const size_t i = blockIdx.x;
+    fast_crop<kPF>(crops[i], fp, sh, hist + i * fp.dim, counts ? counts + i * fp.dim : nullptr);
+}
+
+// Persistent: a fixed grid of workgroups takes crops from a work queue in the
+// order `order` (largest first balances ragged batches) until it runs dry.
+// queue[0] is the next position, queue[1] counts finished workgroups; the
+// last workgroup to finish resets both, so the kernel can be relaunched (or
+// replayed from a graph) with no memset in between.
+template <int kPF>
+__global__ __launch_bounds__(kThreads) void k_features_persistent(
+    const CropDesc *__restrict__ crops, const int32_t *__restrict__ order, int32_t n,
+    FeatParams fp, const uint8_t *__restrict__ tables, float *__restrict__ hist,
+    uint32_t *__restrict__ counts, uint32_t *__restrict__ queue) {
+    __shared__ FastShared sh;
+    load_tables(sh, tables);
+    for (;;) {
+        if (threadIdx.x == 0) sh.next = (int32_t)atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        const int32_t j = sh.next;
+        if (j >= n) break;  // uniform: every thread read the same j
+        const size_t i = order ? (size_t)order[j] : (size_t)j;
+        fast_crop<kPF>(crops[i], fp, sh, hist + i * fp.dim, counts ? counts + i * fp.dim : nullptr);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {
+            atomicExch(&queue[0], 0u);
+            atomicExch(&queue[1], 0u);
         }
     }
 }
@@ -710,11 +758,27 @@ bool fast_path_ok(const FeatParams &fp) {
 
 hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &fp,
                            const uint8_t *d_tables, float *hist, uint32_t *counts,
-                           hipStream_t s) {
+                           hipStream_t s, const LaunchCfg &lc, const int32_t *order,
+                           uint32_t *queue, int32_t num_cus) {
     if (n <= 0) return hipSuccess;
     if (fast_path_ok(fp)) {
-        hipLaunchKernelGGL(k_features_fast, dim3(n), dim3(kThreads), 0, s, crops, fp, d_tables,
-                           hist, counts);
+        const bool pf2 = lc.row_prefetch <= 2;
+        if (lc.persistent && queue) {
+            const int grid = std::min<int>(n, std::max(1, lc.wg_per_cu) * num_cus);
+            const int32_t *ord = lc.sorted ? order : nullptr;
+            if (pf2)
+                hipLaunchKernelGGL(k_features_persistent<2>, dim3(grid), dim3(kThreads), 0, s,
+                                   crops, ord, n, fp, d_tables, hist, counts, queue);
+            else
+                hipLaunchKernelGGL(k_features_persistent<4>, dim3(grid), dim3(kThreads), 0, s,
+                                   crops, ord, n, fp, d_tables, hist, counts, queue);
+        } else if (pf2) {
+            hipLaunchKernelGGL(k_features_fast<2>, dim3(n), dim3(kThreads), 0, s, crops, fp,
+                               d_tables, hist, counts);
+        } else {
+            hipLaunchKernelGGL(k_features_fast<4>, dim3(n), dim3(kThreads), 0, s, crops, fp,
+                               d_tables, hist, counts);
+        }
         return hipGetLastError();
     }
     const size_t shmem = (size_t)fp.dim * sizeof(uint32_t);

@@ -41,13 +41,31 @@ void build_uniform59(uint8_t out[256]);
 void build_comparison_luts(const uint8_t bin[256], uint8_t grey[256], uint8_t depth[256]);
 bool fast_path_ok(const FeatParams &fp);
 
+// Launch shape of the fast feature kernel (chosen per batch by the tuner).
+struct LaunchCfg {
+    int32_t persistent = 0;    // 0: one workgroup per crop; 1: persistent work queue
+    int32_t wg_per_cu = 4;     // persistent grid = wg_per_cu * CUs
+    int32_t row_prefetch = 4;  // rows loaded ahead by each lane (2 or 4)
+    int32_t sorted = 1;        // persistent: take crops largest first
+};
+
 // Kernel launchers (features.hip). All return hipSuccess or the launch error.
+// order / queue may be null (then the launch is one workgroup per crop).
 hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &fp,
                            const uint8_t *d_tables, float *hist, uint32_t *counts,
-                           hipStream_t s);
+                           hipStream_t s, const LaunchCfg &lc = LaunchCfg(),
+                           const int32_t *order = nullptr, uint32_t *queue = nullptr,
+                           int32_t num_cus = 256);
 hipError_t launch_debug_codes(const CropDesc *crop, const FeatParams &fp, uint8_t *gcodes,
                               uint8_t *dcodes, uint8_t *mask, int32_t w, int32_t h,
                               hipStream_t s);
+
+// The plain unbatched comparator (plain.hip): one crop / one row per call.
+hipError_t launch_plain_features(const CropDesc &c, const FeatParams &fp, const uint8_t *bins,
+                                 int32_t *median_scratch, uint32_t *counts, float *row,
+                                 hipStream_t s);
+hipError_t launch_plain_score(const float *x, const float *W, const float *b, int32_t K,
+                              int32_t D, float *scores, int32_t *argmax, hipStream_t s);
 
 // Scoring (score.hip).
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b,

@@ -39,6 +39,7 @@ constexpr int kRing = 4;
 
 struct lbpf_ctx {
     int device = 0;
+    int num_cus = 256;
     lbpf_feature_cfg cfg{};
     FeatParams fp{};
     size_t budget = 0;   // 0 = unbounded
@@ -50,13 +51,25 @@ struct lbpf_ctx {
     int ring_next = 0;
     float *d_scores = nullptr;  // scratch for argmax-only scoring
     size_t scores_elems = 0;
+    int32_t *d_plain_median = nullptr;  // plain path: one crop's median
+    uint32_t *d_plain_counts = nullptr; // plain path: one crop's counts
+    std::vector<CropDesc> h_crops;      // host staging of resolved boxes
 };
 
 struct lbpf_batch {
     lbpf_ctx *ctx = nullptr;
     CropDesc *d_crops = nullptr;
+    int32_t *d_order = nullptr;   // crop indices, largest area first
+    uint32_t *d_queue = nullptr;  // persistent kernel's work queue (self-resetting)
     int32_t n = 0;
     size_t bytes = 0;
+    LaunchCfg lc;
+};
+
+struct lbpf_graph {
+    lbpf_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 struct lbpf_weights {
@@ -177,9 +190,12 @@ lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_
     };
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) return cleanup(fail_hip(e, "hipGetDevice"));
+    e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "hipDeviceGetAttribute"));
 
     const size_t stage_bytes = sizeof(CropDesc) * LBPF_MAX_BOXES_PER_CALL;
-    const size_t ws = 768 + kRing * stage_bytes + kScoreScratchElems * sizeof(float);
+    const size_t ws = 768 + kRing * stage_bytes + kScoreScratchElems * sizeof(float) +
+                      sizeof(int32_t) + sizeof(uint32_t) * (size_t)fp.dim;
     if (!charge(ctx, ws)) return cleanup(fail(LBPF_E_BUDGET, "workspace exceeds the HBM budget"));
 
     // Tables: [0,256) code -> bin; [256,512) grey comparison byte -> bin;
@@ -206,6 +222,10 @@ lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_
     }
     if ((e = hipMalloc((void **)&ctx->d_scores, kScoreScratchElems * sizeof(float))) != hipSuccess)
         return cleanup(fail_hip(e, "hipMalloc"));
+    if ((e = hipMalloc((void **)&ctx->d_plain_median, sizeof(int32_t))) != hipSuccess)
+        return cleanup(fail_hip(e, "hipMalloc"));
+    if ((e = hipMalloc((void **)&ctx->d_plain_counts, sizeof(uint32_t) * fp.dim)) != hipSuccess)
+        return cleanup(fail_hip(e, "hipMalloc"));
     ctx->scores_elems = kScoreScratchElems;
     *out = ctx;
     return LBPF_OK;
@@ -221,6 +241,8 @@ void lbpf_destroy(lbpf_ctx *ctx) {
     }
     if (ctx->d_bins) (void)hipFree(ctx->d_bins);
     if (ctx->d_scores) (void)hipFree(ctx->d_scores);
+    if (ctx->d_plain_median) (void)hipFree(ctx->d_plain_median);
+    if (ctx->d_plain_counts) (void)hipFree(ctx->d_plain_counts);
     delete ctx;
 }
 
@@ -258,7 +280,8 @@ lbpf_status lbpf_batch_create(lbpf_ctx *ctx, const lbpf_image *images, int32_t n
     std::vector<CropDesc> crops;
     lbpf_status st = resolve(ctx, images, n_images, boxes, n_boxes, crops);
     if (st != LBPF_OK) return st;
-    const size_t bytes = sizeof(CropDesc) * (crops.size() ? crops.size() : 1);
+    const size_t nn = crops.size() ? crops.size() : 1;
+    const size_t bytes = (sizeof(CropDesc) + sizeof(int32_t)) * nn + 2 * sizeof(uint32_t);
     if (!charge(ctx, bytes)) return fail(LBPF_E_BUDGET, "batch exceeds the HBM budget");
     lbpf_batch *b = new (std::nothrow) lbpf_batch();
     if (!b) {
@@ -268,9 +291,22 @@ lbpf_status lbpf_batch_create(lbpf_ctx *ctx, const lbpf_image *images, int32_t n
     b->ctx = ctx;
     b->n = n_boxes;
     b->bytes = bytes;
-    hipError_t e = hipMalloc((void **)&b->d_crops, bytes);
+    // Largest crops first: with a dynamic work queue this is longest-
+    // processing-time-first scheduling; ties keep the input order.
+    std::vector<int32_t> order(crops.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        return (int64_t)crops[a].w * crops[a].h > (int64_t)crops[c].w * crops[c].h;
+    });
+    hipError_t e = hipMalloc((void **)&b->d_crops, sizeof(CropDesc) * nn);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_order, sizeof(int32_t) * nn);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_queue, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(b->d_queue, 0, 2 * sizeof(uint32_t));
     if (e == hipSuccess && n_boxes > 0)
         e = hipMemcpy(b->d_crops, crops.data(), sizeof(CropDesc) * crops.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_boxes > 0)
+        e = hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * order.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         lbpf_batch_destroy(b);
@@ -282,10 +318,10 @@ lbpf_status lbpf_batch_create(lbpf_ctx *ctx, const lbpf_image *images, int32_t n
 
 void lbpf_batch_destroy(lbpf_batch *b) {
     if (!b) return;
-    if (b->d_crops) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(b->d_crops);
-    }
+    if (b->d_crops || b->d_order || b->d_queue) (void)hipDeviceSynchronize();
+    if (b->d_crops) (void)hipFree(b->d_crops);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_queue) (void)hipFree(b->d_queue);
     if (b->ctx) b->ctx->used -= b->bytes;
     delete b;
 }
@@ -299,9 +335,141 @@ lbpf_status lbpf_features_batch(lbpf_ctx *ctx, const lbpf_batch *batch, float *h
     if (batch->n == 0) return LBPF_OK;
     if (!hist) return fail(LBPF_E_INVALID, "hist is NULL");
     HIP_TRY(launch_features(batch->d_crops, batch->n, ctx->fp, ctx->d_bins, hist, counts_opt,
-                            (hipStream_t)stream),
+                            (hipStream_t)stream, batch->lc, batch->d_order, batch->d_queue,
+                            ctx->num_cus),
             "feature kernel launch");
     return LBPF_OK;
+}
+
+static bool launch_cfg_valid(const lbpf_launch_cfg &c) {
+    return (c.persistent == 0 || c.persistent == 1) && c.wg_per_cu >= 1 && c.wg_per_cu <= 16 &&
+           (c.row_prefetch == 2 || c.row_prefetch == 4) && (c.sorted == 0 || c.sorted == 1);
+}
+
+lbpf_status lbpf_batch_set_launch(lbpf_batch *batch, const lbpf_launch_cfg *cfg) {
+    if (!batch || !cfg || !launch_cfg_valid(*cfg)) return fail(LBPF_E_INVALID, "bad launch config");
+    batch->lc.persistent = cfg->persistent;
+    batch->lc.wg_per_cu = cfg->wg_per_cu;
+    batch->lc.row_prefetch = cfg->row_prefetch;
+    batch->lc.sorted = cfg->sorted;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_get_launch(const lbpf_batch *batch, lbpf_launch_cfg *cfg) {
+    if (!batch || !cfg) return fail(LBPF_E_INVALID, "NULL argument");
+    *cfg = lbpf_launch_cfg{batch->lc.persistent, batch->lc.wg_per_cu, batch->lc.row_prefetch,
+                           batch->lc.sorted};
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_tune_batch(lbpf_ctx *ctx, lbpf_batch *batch, float *hist, int32_t reps,
+                            lbpf_launch_cfg *best_out, float *best_us_out, void *stream) {
+    if (!ctx || !batch || !hist || reps < 1) return fail(LBPF_E_INVALID, "bad tuning arguments");
+    if (batch->ctx != ctx) return fail(LBPF_E_INVALID, "batch belongs to another context");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<lbpf_launch_cfg> cands;
+    for (int pf : {2, 4}) cands.push_back({0, 4, pf, 1});
+    for (int m : {2, 3, 4})
+        for (int pf : {2, 4})
+            for (int so : {0, 1}) cands.push_back({1, m, pf, so});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t er = hipEventCreate(&e1);
+    if (er != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail_hip(er, "hipEventCreate");
+    }
+    const LaunchCfg saved = batch->lc;
+    float best = 0.f;
+    lbpf_launch_cfg best_cfg = cands[0];
+    lbpf_status st = LBPF_OK;
+    for (const auto &cand : cands) {
+        lbpf_batch_set_launch(batch, &cand);
+        er = launch_features(batch->d_crops, batch->n, ctx->fp, ctx->d_bins, hist, nullptr, s,
+                             batch->lc, batch->d_order, batch->d_queue, ctx->num_cus);
+        if (er == hipSuccess) er = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && er == hipSuccess; ++r)
+            er = launch_features(batch->d_crops, batch->n, ctx->fp, ctx->d_bins, hist, nullptr, s,
+                                 batch->lc, batch->d_order, batch->d_queue, ctx->num_cus);
+        if (er == hipSuccess) er = hipEventRecord(e1, s);
+        if (er == hipSuccess) er = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
+        if (er != hipSuccess) {
+            st = fail_hip(er, "tuning run");
+            break;
+        }
+        const float us = 1000.f * ms / (float)reps;
+        if (best == 0.f || us < best) {
+            best = us;
+            best_cfg = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    batch->lc = saved;
+    if (st != LBPF_OK) return st;
+    lbpf_batch_set_launch(batch, &best_cfg);
+    if (best_out) *best_out = best_cfg;
+    if (best_us_out) *best_us_out = best;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_graph_create(lbpf_ctx *ctx, const lbpf_batch *batch, const lbpf_weights *w,
+                              float *hist, float *scores_opt, int32_t *argmax_opt,
+                              lbpf_graph **out) {
+    if (!ctx || !batch || !hist || !out) return fail(LBPF_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (batch->ctx != ctx || (w && w->ctx != ctx))
+        return fail(LBPF_E_INVALID, "batch or weights belong to another context");
+    if (w && !scores_opt && !argmax_opt) return fail(LBPF_E_INVALID, "no scoring output");
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    lbpf_graph *g = new (std::nothrow) lbpf_graph();
+    if (!g) {
+        (void)hipStreamDestroy(cs);
+        return fail(LBPF_E_BUDGET, "out of host memory");
+    }
+    g->ctx = ctx;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    lbpf_status st = LBPF_OK;
+    if (e == hipSuccess) {
+        st = lbpf_features_batch(ctx, batch, hist, nullptr, cs);
+        if (st == LBPF_OK && w) st = lbpf_score(ctx, hist, batch->n, w, scores_opt, argmax_opt, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        g->graph = graph;
+        if (st == LBPF_OK && e2 != hipSuccess) st = fail_hip(e2, "hipStreamEndCapture");
+    } else {
+        st = fail_hip(e, "hipStreamBeginCapture");
+    }
+    if (st == LBPF_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = fail_hip(e, "hipGraphInstantiate");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != LBPF_OK) {
+        lbpf_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_graph_launch(lbpf_graph *g, void *stream) {
+    if (!g || !g->exec) return fail(LBPF_E_INVALID, "NULL graph");
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
+    return LBPF_OK;
+}
+
+void lbpf_graph_destroy(lbpf_graph *g) {
+    if (!g) return;
+    if (g->exec) {
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(g->exec);
+    }
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, int32_t K,
@@ -369,6 +537,42 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
                                  ctx->d_scores, s),
                 "score launch");
         HIP_TRY(launch_argmax(ctx->d_scores, n, w->K, argmax_opt + n0, s), "argmax launch");
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_features_plain(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                                const lbpf_box *boxes, int32_t n_boxes, float *hist,
+                                uint32_t *counts_opt, void *stream) {
+    if (!ctx) return fail(LBPF_E_INVALID, "ctx is NULL");
+    if (n_boxes > 0 && !hist) return fail(LBPF_E_INVALID, "hist is NULL");
+    lbpf_status st = resolve(ctx, images, n_images, boxes, n_boxes, ctx->h_crops);
+    if (st != LBPF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t D = (size_t)ctx->fp.dim;
+    for (int32_t i = 0; i < n_boxes; ++i) {
+        uint32_t *cnt = counts_opt ? counts_opt + (size_t)i * D : ctx->d_plain_counts;
+        HIP_TRY(launch_plain_features(ctx->h_crops[(size_t)i], ctx->fp, ctx->d_bins,
+                                      ctx->d_plain_median, cnt, hist + (size_t)i * D, s),
+                "plain feature launch");
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_score_plain(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_weights *w,
+                             float *scores_opt, int32_t *argmax_opt, void *stream) {
+    if (!ctx || !w) return fail(LBPF_E_INVALID, "NULL argument");
+    if (w->ctx != ctx) return fail(LBPF_E_INVALID, "weights belong to another context");
+    if (N < 0) return fail(LBPF_E_INVALID, "N < 0");
+    if (!scores_opt && !argmax_opt) return fail(LBPF_E_INVALID, "no output requested");
+    if (N > 0 && !hist) return fail(LBPF_E_INVALID, "hist is NULL");
+    if (w->prec != LBPF_FP32) return fail(LBPF_E_UNSUPPORTED, "the plain path scores in FP32 only");
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t n = 0; n < N; ++n) {
+        float *srow = scores_opt ? scores_opt + (size_t)n * w->K : ctx->d_scores;
+        HIP_TRY(launch_plain_score(hist + (size_t)n * w->D, w->W, w->b, w->K, w->D, srow,
+                                   argmax_opt ? argmax_opt + n : nullptr, s),
+                "plain score launch");
     }
     return LBPF_OK;
 }

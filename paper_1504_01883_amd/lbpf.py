@@ -29,7 +29,9 @@ EXPORTS = [
     "lbpf_version", "lbpf_create", "lbpf_destroy", "lbpf_feature_dim", "lbpf_features",
     "lbpf_batch_create", "lbpf_batch_destroy", "lbpf_batch_size", "lbpf_features_batch",
     "lbpf_weights_create", "lbpf_weights_destroy", "lbpf_weights_count", "lbpf_score",
-    "lbpf_debug_codes", "lbpf_status_string", "lbpf_last_error",
+    "lbpf_debug_codes", "lbpf_status_string", "lbpf_last_error", "lbpf_features_plain",
+    "lbpf_score_plain", "lbpf_batch_set_launch", "lbpf_batch_get_launch", "lbpf_tune_batch",
+    "lbpf_graph_create", "lbpf_graph_launch", "lbpf_graph_destroy",
 ]
 
 
@@ -48,6 +50,14 @@ class Image(ctypes.Structure):
 class Box(ctypes.Structure):
     _fields_ = [("image", ctypes.c_int32), ("x", ctypes.c_int32), ("y", ctypes.c_int32),
                 ("w", ctypes.c_int32), ("h", ctypes.c_int32)]
+
+
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("row_prefetch", ctypes.c_int32), ("sorted", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class FeatureCfg(ctypes.Structure):
@@ -85,6 +95,14 @@ def load():
         "lbpf_weights_count": (i32, [vp]),
         "lbpf_score": (st, [vp, vp, i32, vp, vp, vp, vp]),
         "lbpf_debug_codes": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "lbpf_features_plain": (st, [vp, vp, i32, vp, i32, vp, vp, vp]),
+        "lbpf_score_plain": (st, [vp, vp, i32, vp, vp, vp, vp]),
+        "lbpf_batch_set_launch": (st, [vp, vp]),
+        "lbpf_batch_get_launch": (st, [vp, vp]),
+        "lbpf_tune_batch": (st, [vp, vp, vp, i32, vp, vp, vp]),
+        "lbpf_graph_create": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "lbpf_graph_launch": (st, [vp, vp]),
+        "lbpf_graph_destroy": (None, [vp]),
         "lbpf_status_string": (ctypes.c_char_p, [st]),
         "lbpf_last_error": (ctypes.c_char_p, []),
     }
@@ -158,6 +176,15 @@ class Batch:
         self._h = h
         self.n = n
 
+    def set_launch(self, persistent=0, wg_per_cu=4, row_prefetch=4, sorted=1):
+        cfg = LaunchCfg(persistent, wg_per_cu, row_prefetch, sorted)
+        _check(load().lbpf_batch_set_launch(self._h, ctypes.byref(cfg)))
+
+    def get_launch(self) -> dict:
+        cfg = LaunchCfg()
+        _check(load().lbpf_batch_get_launch(self._h, ctypes.byref(cfg)))
+        return cfg.as_dict()
+
     def close(self):
         if self._h:
             load().lbpf_batch_destroy(self._h)
@@ -189,6 +216,32 @@ class Weights:
     def close(self):
         if self._h:
             load().lbpf_weights_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured, instantiated HIP graph of features (+ scores/argmax)."""
+
+    def __init__(self, ctx: "Context", batch: Batch, weights, hist, scores=None, argmax=None):
+        self._keep = (ctx, batch, weights, hist, scores, argmax)
+        h = ctypes.c_void_p()
+        _check(load().lbpf_graph_create(ctx._h, batch._h, weights._h if weights else None,
+                                        _dptr(hist), _dptr(scores), _dptr(argmax),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(load().lbpf_graph_launch(self._h, _stream()))
+
+    def close(self):
+        if self._h:
+            load().lbpf_graph_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -234,6 +287,31 @@ class Context:
                                     _dptr(cnt), _stream()))
         return hist, cnt
 
+    def features_plain(self, planes, boxes, with_counts=False, out=None):
+        """The plain unbatched comparator path (same results, per-crop launches)."""
+        imgs = make_images(planes)
+        bx, n = make_boxes(boxes)
+        dev = planes[0][1].device if planes else torch.device("cuda")
+        hist = out if out is not None else torch.empty((n, self.dim), dtype=torch.float32,
+                                                       device=dev)
+        cnt = torch.empty((n, self.dim), dtype=torch.int32, device=dev) if with_counts else None
+        _check(load().lbpf_features_plain(self._h, imgs, len(planes), bx, n, _dptr(hist),
+                                          _dptr(cnt), _stream()))
+        return hist, cnt
+
+    def score_plain(self, hist: torch.Tensor, weights: "Weights", want_scores=True,
+                    want_argmax=True, scores_out=None, argmax_out=None):
+        hist = hist.contiguous()
+        N = hist.shape[0]
+        S = scores_out if scores_out is not None else (
+            torch.empty((N, weights.K), dtype=torch.float32, device=hist.device)
+            if want_scores else None)
+        A = argmax_out if argmax_out is not None else (
+            torch.empty((N,), dtype=torch.int32, device=hist.device) if want_argmax else None)
+        _check(load().lbpf_score_plain(self._h, _dptr(hist), N, weights._h, _dptr(S), _dptr(A),
+                                       _stream()))
+        return S, A
+
     def batch(self, planes, boxes) -> Batch:
         return Batch(self, planes, boxes)
 
@@ -243,6 +321,17 @@ class Context:
         _check(load().lbpf_features_batch(self._h, batch._h, _dptr(out), _dptr(counts_out),
                                           _stream()))
         return out
+
+    def tune(self, batch: Batch, hist: torch.Tensor, reps: int = 5):
+        """Time every launch shape on `batch`, keep the fastest; -> (cfg dict, us)."""
+        best = LaunchCfg()
+        us = ctypes.c_float()
+        _check(load().lbpf_tune_batch(self._h, batch._h, _dptr(hist), reps, ctypes.byref(best),
+                                      ctypes.byref(us), _stream()))
+        return best.as_dict(), float(us.value)
+
+    def graph(self, batch: Batch, hist, weights=None, scores=None, argmax=None) -> Graph:
+        return Graph(self, batch, weights, hist, scores, argmax)
 
     def weights(self, W: torch.Tensor, b: torch.Tensor, precision="fp32") -> Weights:
         return Weights(self, W, b, precision)

@@ -227,3 +227,19 @@ def test_end_to_end_tiny_with_trained_weights(ctx, ref):
     acc = float((A.cpu().numpy() == labels).mean())
     print(f"tiny workload recognition accuracy (synthetic): {acc:.3f}")
     assert acc >= 0.9
+
+
+def test_plain_path_matches_oracle(ctx, ref):
+    """The plain unbatched comparator computes the same features bit for bit and
+    FP32 scores within the tolerance."""
+    g, z, _ = synth.make_crops(12, 128, 128, synth.W_UNIFORM, 256)
+    planes, boxes = stacked_planes(g, z)
+    hist, cnt = ctx.features_plain(planes, boxes, with_counts=True)
+    W, b = synth.synthetic_weights(40, ctx.dim, synth.W_UNIFORM)
+    wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda())
+    S, A = ctx.score_plain(hist, wts)
+    torch.cuda.synchronize()
+    hp, _ = host_planes(g, z)
+    f, c, _ = ref.features(hp, boxes, n_threads=8)
+    _assert_bitexact(hist.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), f, c)
+    _check_scores(S.cpu().numpy(), A.cpu().numpy(), f, W, b, ref)
