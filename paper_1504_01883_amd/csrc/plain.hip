@@ -6,7 +6,7 @@
 //   2. one thread per interior pixel computes both LBP codes and increments
 //      the crop's histogram with global-memory atomics;
 //   3. one thread per element normalises the counts into the feature row;
-//   4. one thread per identity computes its decision value (a GEMV), and one
+//   4. one wave per identity computes its decision value (a GEMV), and one
 //      wave takes the argmax.
 // Five launches per crop, no shared memory beyond the median's.
 #include "lbpf_internal.h"
@@ -31,9 +31,38 @@ __device__ __forceinline__ uint32_t plain_code(const T *p, int32_t pitch, int y,
     return code;
 }
 
-// Median by a two-level radix select over 256-bin shared histograms.
+// Median by a two-level radix select over 256-bin shared histograms; the
+// bin holding the rank is found by one wave with a prefix scan.
+__device__ __forceinline__ void plain_select(const uint32_t *h, uint32_t rank, int32_t *sel,
+                                             uint32_t *sel_rank) {
+    const int lane = threadIdx.x;
+    uint32_t c[4], s = 0;
+    for (int j = 0; j < 4; ++j) {
+        c[j] = h[4 * lane + j];
+        s += c[j];
+    }
+    uint32_t incl = s;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    uint32_t acc = incl - s;
+    if (lane == 0) *sel = -1;
+    if (acc <= rank && rank < incl) {
+        for (int j = 0; j < 4; ++j) {
+            if (rank < acc + c[j]) {
+                *sel = 4 * lane + j;
+                *sel_rank = rank - acc;
+                break;
+            }
+            acc += c[j];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_plain_median(CropDesc c, int32_t *median) {
     __shared__ uint32_t h[256];
+    __shared__ uint32_t total;
     __shared__ int32_t sel;
     __shared__ uint32_t sel_rank;
     const int tid = threadIdx.x;
@@ -41,29 +70,21 @@ __global__ __launch_bounds__(kThreads) void k_plain_median(CropDesc c, int32_t *
     uint32_t rank = 0;
     for (int level = 0; level < 2; ++level) {
         h[tid] = 0;
+        if (tid == 0) total = 0;
         __syncthreads();
-        for (int i = tid; i < c.w * c.h; i += kThreads) {
-            const uint32_t d = c.depth[(size_t)(i / c.w) * c.depth_pitch + (i % c.w)];
-            if (d == 0) continue;
-            if (level == 0) atomicAdd(&h[d >> 8], 1u);
-            else if ((int32_t)(d >> 8) == hi) atomicAdd(&h[d & 255u], 1u);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t total = 0;
-            for (int b = 0; b < 256; ++b) total += h[b];
-            const uint32_t target = level == 0 ? (total ? (total - 1) / 2 : 0) : rank;
-            sel = -1;
-            uint32_t acc = 0;
-            for (int b = 0; b < 256 && total; ++b) {
-                if (target < acc + h[b]) {
-                    sel = b;
-                    sel_rank = target - acc;
-                    break;
-                }
-                acc += h[b];
+        uint32_t nz = 0;
+        for (int y = 0; y < c.h; ++y)
+            for (int x = tid; x < c.w; x += kThreads) {
+                const uint32_t d = c.depth[(size_t)y * c.depth_pitch + x];
+                if (d == 0) continue;
+                nz += 1;
+                if (level == 0) atomicAdd(&h[d >> 8], 1u);
+                else if ((int32_t)(d >> 8) == hi) atomicAdd(&h[d & 255u], 1u);
             }
-        }
+        if (level == 0) atomicAdd(&total, nz);
+        __syncthreads();
+        if (tid < 64) plain_select(h, level == 0 ? (total ? (total - 1) / 2 : 1u << 31) : rank, &sel,
+                                   &sel_rank);
         __syncthreads();
         if (level == 0) {
             hi = sel;
@@ -120,18 +141,19 @@ __global__ __launch_bounds__(kThreads) void k_plain_normalise(const uint32_t *co
         row[i] = T ? (float)counts[i] / (float)T : 0.0f;
 }
 
+// One wave per identity: lanes stride over the row (coalesced), then a
+// butterfly sum.
 __global__ __launch_bounds__(kThreads) void k_plain_gemv(const float *x, const float *W,
                                                          const float *b, int32_t K, int32_t D,
                                                          float *s) {
-    const int k = blockIdx.x * kThreads + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     if (k >= K) return;
     const float *w = W + (size_t)k * D;
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // 8 interleaved partial sums
-    int d = 0;
-    for (; d + 8 <= D; d += 8)
-        for (int u = 0; u < 8; ++u) acc[u] = fmaf(w[d + u], x[d + u], acc[u]);
-    for (; d < D; ++d) acc[d & 7] = fmaf(w[d], x[d], acc[d & 7]);
-    s[k] = (((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]))) + b[k];
+    float acc = 0.0f;
+    for (int d = lane; d < D; d += 64) acc = fmaf(w[d], x[d], acc);
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) s[k] = acc + b[k];
 }
 
 __global__ __launch_bounds__(64) void k_plain_argmax(const float *s, int32_t K, int32_t *out) {
@@ -171,8 +193,9 @@ hipError_t launch_plain_features(const CropDesc &c, const FeatParams &fp, const 
 
 hipError_t launch_plain_score(const float *x, const float *W, const float *b, int32_t K,
                               int32_t D, float *scores, int32_t *argmax, hipStream_t s) {
-    hipLaunchKernelGGL(k_plain_gemv, dim3((K + kThreads - 1) / kThreads), dim3(kThreads), 0, s, x,
-                       W, b, K, D, scores);
+    const int per_block = kThreads / 64;
+    hipLaunchKernelGGL(k_plain_gemv, dim3((K + per_block - 1) / per_block), dim3(kThreads), 0, s,
+                       x, W, b, K, D, scores);
     if (argmax) hipLaunchKernelGGL(k_plain_argmax, dim3(1), dim3(64), 0, s, scores, K, argmax);
     return hipGetLastError();
 }
