@@ -15,7 +15,7 @@ CSRC = PKG / "csrc"
 OBJ = PKG / "_build"
 LIB = PKG / "liblbpf.so"
 
-SOURCES = ["features.hip", "score.hip", "plain.hip", "runtime.cpp", "tables.cpp"]
+SOURCES = ["features.hip", "score.hip", "score_lp.hip", "plain.hip", "runtime.cpp", "tables.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

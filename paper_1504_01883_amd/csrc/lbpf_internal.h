@@ -67,6 +67,15 @@ hipError_t launch_plain_features(const CropDesc &c, const FeatParams &fp, const 
 hipError_t launch_plain_score(const float *x, const float *W, const float *b, int32_t K,
                               int32_t D, float *scores, int32_t *argmax, hipStream_t s);
 
+// Reduced-precision scoring (score_lp.hip). Quantised rows have a pitch of
+// lp_pitch(D, mode) bytes (a multiple of 128, zero padded).
+int32_t lp_pitch(int32_t D, int32_t mode);
+hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mode, uint8_t *out,
+                             float *scales, hipStream_t s);
+hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const uint8_t *Wq,
+                           const float *sw, const float *b, int32_t K, int32_t D, int32_t mode,
+                           float *S, hipStream_t s);
+
 // Scoring (score.hip).
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b,
                             int32_t K, int32_t D, float *S, hipStream_t s);

@@ -54,6 +54,9 @@ struct lbpf_ctx {
     int32_t *d_plain_median = nullptr;  // plain path: one crop's median
     uint32_t *d_plain_counts = nullptr; // plain path: one crop's counts
     std::vector<CropDesc> h_crops;      // host staging of resolved boxes
+    uint8_t *d_xq = nullptr;            // reduced-precision scoring: quantised feature rows
+    float *d_sx = nullptr;              //   and their scales, kLpChunkRows rows
+    size_t xq_bytes = 0;
 };
 
 struct lbpf_batch {
@@ -76,14 +79,17 @@ struct lbpf_weights {
     lbpf_ctx *ctx = nullptr;
     int32_t K = 0, D = 0;
     lbpf_precision prec = LBPF_FP32;
-    float *W = nullptr;
+    float *W = nullptr;       // FP32 copy (FP32 precision only)
     float *b = nullptr;
+    uint8_t *Wq = nullptr;    // quantised rows (reduced precision)
+    float *sw = nullptr;      // their scales
     size_t bytes = 0;
 };
 
 namespace {
 
 constexpr size_t kScoreScratchElems = size_t(16) << 20;  // 64 MiB of FP32 scores
+constexpr int32_t kLpChunkRows = 16384;                  // feature rows quantised per pass
 
 bool charge(lbpf_ctx *ctx, size_t bytes) {
     if (ctx->budget && ctx->used + bytes > ctx->budget) return false;
@@ -242,6 +248,8 @@ void lbpf_destroy(lbpf_ctx *ctx) {
     if (ctx->d_bins) (void)hipFree(ctx->d_bins);
     if (ctx->d_scores) (void)hipFree(ctx->d_scores);
     if (ctx->d_plain_median) (void)hipFree(ctx->d_plain_median);
+    if (ctx->d_xq) (void)hipFree(ctx->d_xq);
+    if (ctx->d_sx) (void)hipFree(ctx->d_sx);
     if (ctx->d_plain_counts) (void)hipFree(ctx->d_plain_counts);
     delete ctx;
 }
@@ -476,13 +484,23 @@ lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, i
                                 lbpf_precision precision, lbpf_weights **out, void *stream) {
     if (!ctx || !W || !b || !out || K < 1) return fail(LBPF_E_INVALID, "bad weights arguments");
     *out = nullptr;
-    if (precision != LBPF_FP32) return fail(LBPF_E_UNSUPPORTED, "precision not built");
+    if (precision < LBPF_FP32 || precision > LBPF_FP8_E4M3)
+        return fail(LBPF_E_UNSUPPORTED, "unknown precision");
     const int32_t D = ctx->fp.dim;
-    const size_t wbytes = sizeof(float) * (size_t)K * D, bbytes = sizeof(float) * (size_t)K;
-    if (!charge(ctx, wbytes + bbytes)) return fail(LBPF_E_BUDGET, "weights exceed the HBM budget");
+    const bool lp = precision != LBPF_FP32;
+    const size_t bbytes = sizeof(float) * (size_t)K;
+    const size_t wbytes = lp ? (size_t)K * lp_pitch(D, precision) + bbytes
+                             : sizeof(float) * (size_t)K * D;
+    // The first reduced-precision weights also size the context's feature
+    // quantisation scratch (kLpChunkRows rows at the widest pitch).
+    const size_t xq_need =
+        (lp && !ctx->d_xq) ? (size_t)kLpChunkRows * lp_pitch(D, LBPF_BF16) : 0;
+    const size_t sx_need = xq_need ? sizeof(float) * kLpChunkRows : 0;
+    if (!charge(ctx, wbytes + bbytes + xq_need + sx_need))
+        return fail(LBPF_E_BUDGET, "weights exceed the HBM budget");
     lbpf_weights *w = new (std::nothrow) lbpf_weights();
     if (!w) {
-        ctx->used -= wbytes + bbytes;
+        ctx->used -= wbytes + bbytes + xq_need + sx_need;
         return fail(LBPF_E_BUDGET, "out of host memory");
     }
     w->ctx = ctx;
@@ -491,10 +509,22 @@ lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, i
     w->prec = precision;
     w->bytes = wbytes + bbytes;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMalloc((void **)&w->W, wbytes);
-    if (e == hipSuccess) e = hipMalloc((void **)&w->b, bbytes);
-    if (e == hipSuccess) e = hipMemcpyAsync(w->W, W, wbytes, hipMemcpyDeviceToDevice, s);
+    hipError_t e = hipMalloc((void **)&w->b, bbytes);
     if (e == hipSuccess) e = hipMemcpyAsync(w->b, b, bbytes, hipMemcpyDeviceToDevice, s);
+    if (!lp) {
+        if (e == hipSuccess) e = hipMalloc((void **)&w->W, sizeof(float) * (size_t)K * D);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(w->W, W, sizeof(float) * (size_t)K * D, hipMemcpyDeviceToDevice, s);
+    } else {
+        if (e == hipSuccess) e = hipMalloc((void **)&w->Wq, (size_t)K * lp_pitch(D, precision));
+        if (e == hipSuccess) e = hipMalloc((void **)&w->sw, bbytes);
+        if (e == hipSuccess) e = launch_quant_rows(W, K, D, precision, w->Wq, w->sw, s);
+        if (e == hipSuccess && xq_need) {
+            e = hipMalloc((void **)&ctx->d_xq, xq_need);
+            if (e == hipSuccess) e = hipMalloc((void **)&ctx->d_sx, sx_need);
+            if (e == hipSuccess) ctx->xq_bytes = xq_need;
+        }
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         lbpf_weights_destroy(w);
@@ -506,9 +536,11 @@ lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, i
 
 void lbpf_weights_destroy(lbpf_weights *w) {
     if (!w) return;
-    if (w->W || w->b) (void)hipDeviceSynchronize();
+    if (w->W || w->b || w->Wq) (void)hipDeviceSynchronize();
     if (w->W) (void)hipFree(w->W);
     if (w->b) (void)hipFree(w->b);
+    if (w->Wq) (void)hipFree(w->Wq);
+    if (w->sw) (void)hipFree(w->sw);
     if (w->ctx) w->ctx->used -= w->bytes;
     delete w;
 }
@@ -524,19 +556,26 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
     if (N == 0) return LBPF_OK;
     if (!hist) return fail(LBPF_E_INVALID, "hist is NULL");
     hipStream_t s = (hipStream_t)stream;
-    if (scores_opt) {
-        HIP_TRY(launch_score_f32(hist, N, w->W, w->b, w->K, w->D, scores_opt, s), "score launch");
-        if (argmax_opt) HIP_TRY(launch_argmax(scores_opt, N, w->K, argmax_opt, s), "argmax launch");
-        return LBPF_OK;
-    }
-    // Argmax only: score in chunks of rows through the context's scratch.
-    const int32_t rows = (int32_t)std::max<size_t>(1, ctx->scores_elems / (size_t)w->K);
+    const size_t K = (size_t)w->K, D = (size_t)w->D;
+    // Rows per pass: all of them when scores go to the caller's buffer,
+    // otherwise as many as the context's score scratch holds.
+    int32_t rows = scores_opt ? N : (int32_t)std::max<size_t>(1, ctx->scores_elems / K);
+    if (w->prec != LBPF_FP32) rows = std::min(rows, kLpChunkRows);
     for (int32_t n0 = 0; n0 < N; n0 += rows) {
         const int32_t n = std::min(rows, N - n0);
-        HIP_TRY(launch_score_f32(hist + (size_t)n0 * w->D, n, w->W, w->b, w->K, w->D,
-                                 ctx->d_scores, s),
-                "score launch");
-        HIP_TRY(launch_argmax(ctx->d_scores, n, w->K, argmax_opt + n0, s), "argmax launch");
+        float *S = scores_opt ? scores_opt + (size_t)n0 * K : ctx->d_scores;
+        if (w->prec == LBPF_FP32) {
+            HIP_TRY(launch_score_f32(hist + (size_t)n0 * D, n, w->W, w->b, w->K, w->D, S, s),
+                    "score launch");
+        } else {
+            HIP_TRY(launch_quant_rows(hist + (size_t)n0 * D, n, w->D, w->prec, ctx->d_xq,
+                                      ctx->d_sx, s),
+                    "quantise launch");
+            HIP_TRY(launch_score_lp(ctx->d_xq, ctx->d_sx, n, w->Wq, w->sw, w->b, w->K, w->D,
+                                    w->prec, S, s),
+                    "score launch");
+        }
+        if (argmax_opt) HIP_TRY(launch_argmax(S, n, w->K, argmax_opt + n0, s), "argmax launch");
     }
     return LBPF_OK;
 }

@@ -1,0 +1,288 @@
+// Reduced-precision SVM scoring, S = (s_x[n] s_w[k]) (Xq Wq^T)[n][k] + b[k],
+// on gfx950 matrix cores with FP32 accumulation (Sec. 2.5 decision values).
+//
+// Operand formats (rows quantised by k_quant_rows):
+//   BF16: round-to-nearest-even, no scale (s = 1);
+//   FP16: per-row power-of-two scale s = 2^(e - 14), e = exponent of the row's
+//         largest magnitude, so the row's largest value lands in [2^14, 2^15)
+//         and the scaling itself is exact;
+//   FP8 : OCP e4m3 (bias 7, max 448, no infinities), per-row scale
+//         s = amax / 448, x / s rounded to nearest even and saturated.
+// Quantised rows are stored with a row pitch rounded up to 128 bytes, zero
+// padded, so every k-stage of the GEMM is a whole 128-byte chunk.
+//
+// GEMM: a workgroup of 4 wave64 owns a 256 (n) x 128 (k) tile of S; wave w
+// owns rows 128 (w & 1) .. +128 and columns 64 (w >> 1) .. +64 as 4 x 2
+// blocks of 32 x 32 (v_mfma_f32_32x32x16_{bf16,f16} or
+// v_mfma_f32_32x32x64_f8f6f4). Per k-stage of 128 bytes per row the
+// workgroup stages its A (256 x 128 B) and B (128 x 128 B) tiles in LDS (rows
+// padded to 144 B so the 16-byte fragment reads of 8 consecutive rows cover
+// all 32 banks), and the next stage's tiles are loaded into registers while
+// the current one is multiplied.
+#include "lbpf_internal.h"
+
+namespace lbpf {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTM = 256, kTN = 128;  // workgroup tile
+constexpr int kRowB = 128;           // bytes of k per stage and row
+constexpr int kPitch = 144;          // LDS row pitch (bytes)
+
+// --- conversions ------------------------------------------------------------
+
+__device__ __forceinline__ uint16_t to_bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+
+__device__ __forceinline__ uint16_t to_f16_rne(float f) {
+    return __builtin_bit_cast(uint16_t, (_Float16)f);  // IEEE conversion, round to nearest even
+}
+
+// OCP e4m3: 1 sign, 4 exponent (bias 7), 3 mantissa bits; finite values
+// 2^-9 .. 448; saturating, round to nearest even.
+__device__ __forceinline__ uint8_t to_e4m3_rne_sat(float f) {
+    const uint32_t sign = (__float_as_uint(f) >> 24) & 0x80u;
+    float a = fabsf(f);
+    if (!(a < 448.0f)) return (uint8_t)(sign | 0x7Eu);  // saturate (NaN too) to 448
+    if (a == 0.0f) return (uint8_t)sign;
+    int e;
+    frexpf(a, &e);                 // a = m 2^e, m in [0.5, 1)
+    int ex = e - 1;                // a in [2^ex, 2^(ex+1))
+    if (ex < -6) ex = -6;          // subnormal range: quantum 2^-9
+    const float q = ldexpf(1.0f, ex - 3);  // spacing of representable values
+    float n = rintf(a / q);        // exact division by a power of two; rint = nearest even
+    // n in [8, 16] for normals (16 rounds up into the next binade), [0, 8) subnormal
+    uint32_t bits;
+    if (n >= 16.0f) {
+        ex += 1;
+        n = 8.0f;
+    }
+    if (ex == -6 && n < 8.0f) {
+        bits = (uint32_t)n;  // subnormal: exponent field 0
+    } else {
+        bits = ((uint32_t)(ex + 7) << 3) | ((uint32_t)n - 8u);
+    }
+    if (bits > 0x7Eu) bits = 0x7Eu;
+    return (uint8_t)(sign | bits);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// One workgroup per row: amax, scale, convert; pads the row to `pitch` bytes.
+template <int kMode>
+__global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ X, int32_t rows,
+                                                    int32_t D, int32_t pitch,
+                                                    uint8_t *__restrict__ out,
+                                                    float *__restrict__ scales) {
+    __shared__ float part[4];
+    const int r = blockIdx.x;
+    const float *x = X + (size_t)r * D;
+    float amax = 0.0f;
+    for (int i = threadIdx.x; i < D; i += 256) amax = fmaxf(amax, fabsf(x[i]));
+    amax = wave_max(amax);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    amax = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+    uint8_t *o = out + (size_t)r * pitch;
+    if (kMode == LBPF_BF16) {
+        if (threadIdx.x == 0) scales[r] = 1.0f;
+        uint16_t *o16 = reinterpret_cast<uint16_t *>(o);
+        for (int i = threadIdx.x; i < pitch / 2; i += 256) o16[i] = i < D ? to_bf16_rne(x[i]) : 0;
+    } else if (kMode == LBPF_FP16) {
+        int e = 0;
+        if (amax > 0.0f) frexpf(amax, &e);  // amax in [2^(e-1), 2^e)
+        const int sh = (amax > 0.0f) ? (e - 1) - 14 : 0;
+        if (threadIdx.x == 0) scales[r] = ldexpf(1.0f, sh);
+        uint16_t *o16 = reinterpret_cast<uint16_t *>(o);
+        for (int i = threadIdx.x; i < pitch / 2; i += 256)
+            o16[i] = i < D ? to_f16_rne(ldexpf(x[i], -sh)) : 0;
+    } else {
+        const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
+        if (threadIdx.x == 0) scales[r] = s;
+        for (int i = threadIdx.x; i < pitch; i += 256) o[i] = i < D ? to_e4m3_rne_sat(x[i] / s) : 0;
+    }
+}
+
+// --- GEMM ----------------------------------------------------------------------
+
+template <int kMode>
+__device__ __forceinline__ f32x16 mfma_step(const u32x4 a[2], const u32x4 b[2], f32x16 acc, int sub) {
+    if constexpr (kMode == LBPF_FP8_E4M3) {
+        // one 32x32x64 step consumes 32 bytes (two 16-byte fragments) per lane
+        const i32x8 av = {(int)a[0].x, (int)a[0].y, (int)a[0].z, (int)a[0].w,
+                          (int)a[1].x, (int)a[1].y, (int)a[1].z, (int)a[1].w};
+        const i32x8 bv = {(int)b[0].x, (int)b[0].y, (int)b[0].z, (int)b[0].w,
+                          (int)b[1].x, (int)b[1].y, (int)b[1].z, (int)b[1].w};
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 0, 0, 0);
+    } else if constexpr (kMode == LBPF_FP16) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a[sub]),
+                                                     __builtin_bit_cast(f16x8, b[sub]), acc, 0, 0, 0);
+    } else {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[sub]),
+                                                      __builtin_bit_cast(bf16x8, b[sub]), acc, 0, 0, 0);
+    }
+}
+
+// Xq: [N][pitch] bytes, Wq: [K][pitch] bytes, pitch a multiple of 128.
+// S: [N][K] FP32 (ld = ldS). Rows past N / K read as zero and are not stored.
+template <int kMode>
+__global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq,
+                                                  const float *__restrict__ sx, int32_t N,
+                                                  const uint8_t *__restrict__ Wq,
+                                                  const float *__restrict__ sw,
+                                                  const float *__restrict__ bias, int32_t K,
+                                                  int32_t pitch, float *__restrict__ S) {
+    __shared__ __attribute__((aligned(16))) uint8_t sA[kTM * kPitch];
+    __shared__ __attribute__((aligned(16))) uint8_t sB[kTN * kPitch];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int32_t n0 = blockIdx.x * kTM, k0 = blockIdx.y * kTN;
+
+    // Global -> register staging: thread t moves 16-byte chunk (t % 8) of rows
+    // t / 8 + 32 j.
+    const int ch = tid & 7, r0 = tid >> 3;
+    u32x4 ra[8], rb[4];
+    auto load_stage = [&](int32_t kb) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int32_t n = n0 + r0 + 32 * j;
+            ra[j] = n < N ? *reinterpret_cast<const u32x4 *>(Xq + (size_t)n * pitch + kb + 16 * ch)
+                          : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t k = k0 + r0 + 32 * j;
+            rb[j] = k < K ? *reinterpret_cast<const u32x4 *>(Wq + (size_t)k * pitch + kb + 16 * ch)
+                          : u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            *reinterpret_cast<u32x4 *>(sA + (r0 + 32 * j) * kPitch + 16 * ch) = ra[j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<u32x4 *>(sB + (r0 + 32 * j) * kPitch + 16 * ch) = rb[j];
+    };
+
+    f32x16 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+
+    const int fr = lane & 31, fq = lane >> 5;  // fragment row, 16-byte half of 32 bytes
+    load_stage(0);
+    for (int32_t kb = 0; kb < pitch; kb += kRowB) {
+        __syncthreads();  // the previous stage's fragments have been read
+        store_stage();
+        __syncthreads();
+        if (kb + kRowB < pitch) load_stage(kb + kRowB);
+        // 4 sub-steps of 32 bytes per row: lane (fr, fq) supplies bytes
+        // 16 fq .. 16 fq + 15 of its row's 32-byte slice; an FP8 step takes
+        // both halves of a 64-byte slice.
+        constexpr int kSubB = (kMode == LBPF_FP8_E4M3) ? 64 : 32;
+#pragma unroll
+        for (int sb = 0; sb < kRowB; sb += kSubB) {
+            u32x4 a[4][2], b[2][2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint8_t *p = sA + (wm * 128 + 32 * i + fr) * kPitch + sb;
+                if constexpr (kMode == LBPF_FP8_E4M3) {
+                    a[i][0] = *reinterpret_cast<const u32x4 *>(p + 32 * fq);
+                    a[i][1] = *reinterpret_cast<const u32x4 *>(p + 32 * fq + 16);
+                } else {
+                    a[i][0] = *reinterpret_cast<const u32x4 *>(p + 16 * fq);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint8_t *p = sB + (wn * 64 + 32 * j + fr) * kPitch + sb;
+                if constexpr (kMode == LBPF_FP8_E4M3) {
+                    b[j][0] = *reinterpret_cast<const u32x4 *>(p + 32 * fq);
+                    b[j][1] = *reinterpret_cast<const u32x4 *>(p + 32 * fq + 16);
+                } else {
+                    b[j][0] = *reinterpret_cast<const u32x4 *>(p + 16 * fq);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma_step<kMode>(a[i], b[j], acc[i][j], 0);
+        }
+    }
+
+    // 32 x 32 block layout: lane l, register r holds row 8 (r / 4) + 4 (l / 32)
+    // + r % 4 and column l % 32.
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int32_t k = k0 + wn * 64 + 32 * j + (lane & 31);
+        if (k >= K) continue;
+        const float swk = sw[k], bk = bias[k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int32_t n = n0 + wm * 128 + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (n < N) S[(size_t)n * K + k] = (sx[n] * swk) * acc[i][j][r] + bk;
+            }
+    }
+}
+
+}  // namespace
+
+int32_t lp_pitch(int32_t D, int32_t mode) {
+    const int32_t bytes = D * (mode == LBPF_FP8_E4M3 ? 1 : 2);
+    return (bytes + kRowB - 1) / kRowB * kRowB;
+}
+
+hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mode, uint8_t *out,
+                             float *scales, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    const int32_t pitch = lp_pitch(D, mode);
+    if (mode == LBPF_BF16)
+        hipLaunchKernelGGL(k_quant_rows<LBPF_BF16>, dim3(rows), dim3(256), 0, s, X, rows, D, pitch,
+                           out, scales);
+    else if (mode == LBPF_FP16)
+        hipLaunchKernelGGL(k_quant_rows<LBPF_FP16>, dim3(rows), dim3(256), 0, s, X, rows, D, pitch,
+                           out, scales);
+    else
+        hipLaunchKernelGGL(k_quant_rows<LBPF_FP8_E4M3>, dim3(rows), dim3(256), 0, s, X, rows, D,
+                           pitch, out, scales);
+    return hipGetLastError();
+}
+
+hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const uint8_t *Wq,
+                           const float *sw, const float *b, int32_t K, int32_t D, int32_t mode,
+                           float *S, hipStream_t s) {
+    if (N <= 0 || K <= 0) return hipSuccess;
+    const int32_t pitch = lp_pitch(D, mode);
+    dim3 grid((N + kTM - 1) / kTM, (K + kTN - 1) / kTN);
+    if (mode == LBPF_BF16)
+        hipLaunchKernelGGL(k_score_lp<LBPF_BF16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,
+                           pitch, S);
+    else if (mode == LBPF_FP16)
+        hipLaunchKernelGGL(k_score_lp<LBPF_FP16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,
+                           pitch, S);
+    else
+        hipLaunchKernelGGL(k_score_lp<LBPF_FP8_E4M3>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b,
+                           K, pitch, S);
+    return hipGetLastError();
+}
+
+}  // namespace lbpf
