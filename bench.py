@@ -47,6 +47,13 @@ def _parse():
                    help="crops of the workload the CPU oracle is timed on")
     p.add_argument("--plain-sample", type=int, default=512,
                    help="crops the plain unbatched GPU path is timed on")
+    p.add_argument("--workload", default="uniform",
+                   choices=["uniform", "ragged", "precision", "serving"],
+                   help="uniform (default): the headline line; the others are the ragged-batch, "
+                        "precision and serving workloads")
+    p.add_argument("--precision-rows", type=int, default=131072)
+    p.add_argument("--precision-identities", type=int, default=8192)
+    p.add_argument("--ragged-crops", type=int, default=16384)
     return p.parse_args()
 
 
@@ -86,6 +93,15 @@ def main():
               "sharding of this path is described in DESIGN.md and not run here.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "ragged":
+        return bench_ragged(args)
+    if args.workload == "precision":
+        return bench_precision(args)
+    if args.workload == "serving":
+        from paper_1504_01883_amd import serve
+        print(json.dumps(serve.bench(args)), flush=True)
+        return None
 
     import torch
 
@@ -203,6 +219,150 @@ def main():
     for bt in batches:
         bt.close()
     wts.close()
+    ctx.close()
+
+
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def bench_ragged(args):
+    """Ragged batch: 16384 crops, sides U{48..256}, aspect U[0.8, 1.25], 8x8
+    proportional cells, 1024 identities (FP32 scores + argmax). The launch shape
+    is picked by the autotuner; the step (features + scores + argmax) is one
+    HIP-graph replay."""
+    import torch
+
+    from paper_1504_01883_amd import lbpf, synth, tune
+    torch.cuda.set_device(0)
+    n, K = args.ragged_crops, 1024
+    t0 = time.time()
+    g, z, offs, sizes, _ = synth.make_ragged(n, K)
+    print(f"[bench] generated {n} ragged crops in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    ctx = lbpf.Context()
+    D = ctx.dim
+    # The pool as one image of width 1 would forbid the 3x3 stencil; instead
+    # each crop is its own image, all views into two device pools.
+    dg = torch.from_numpy(g).cuda()
+    dz = torch.from_numpy(z.view(np.int16)).cuda()
+    planes = []
+    for o, (w, h) in zip(offs, sizes):
+        o, w, h = int(o), int(w), int(h)
+        planes.append((dg[o:o + w * h].view(h, w), dz[o:o + w * h].view(h, w)))
+    boxes = [[i, 0, 0, int(w), int(h)] for i, (w, h) in enumerate(sizes)]
+    batch = ctx.batch(planes, boxes)
+    W, b = synth.synthetic_weights(K, D, synth.W_RAGGED)
+    wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda())
+    hist = torch.empty((n, D), dtype=torch.float32, device="cuda")
+    S = torch.empty((n, K), dtype=torch.float32, device="cuda")
+    A = torch.empty((n,), dtype=torch.int32, device="cuda")
+    area = float((sizes[:, 0] * sizes[:, 1]).mean())
+    tuned = tune.tuned(ctx, batch, hist, n, area, reps=3, retune=True)
+    # Feature kernel alone, eager, with the tuned shape.
+    e = _events(2)
+    ctx.features_batch(batch, hist)
+    torch.cuda.synchronize()
+    e[0].record()
+    for _ in range(args.steps):
+        ctx.features_batch(batch, hist)
+    e[1].record()
+    torch.cuda.synchronize()
+    feat_ms = e[0].elapsed_time(e[1]) / args.steps
+    graph = ctx.graph(batch, hist, wts, S, A)
+    for _ in range(args.warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    e = _events(2)
+    e[0].record()
+    for _ in range(args.steps):
+        graph.launch()
+    e[1].record()
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1]) / args.steps
+    feat_bytes = float(3 * (sizes[:, 0] * sizes[:, 1]).sum() + n * D * 4)
+    gbs = feat_bytes / (feat_ms * 1e-3) / 1e9
+    out = {"metric": "face crops/s (LBP+hist+SVM), ragged batch", "value": n / (ms * 1e-3),
+           "unit": "crops/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"ragged batch: {n} crops, sides 48-256, aspect 0.8-1.25, "
+                                  f"mean area {area:.0f} px, {K} identities, FP32 scoring, "
+                                  "one HIP-graph replay per step", "crops": n,
+                      "identities": K, "dim": D},
+           "tuned_launch": tuned,
+           "features": {"ms": feat_ms, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                        "algorithmic_bytes": feat_bytes}}
+    print(json.dumps(out), flush=True)
+    graph.close()
+    batch.close()
+    wts.close()
+    ctx.close()
+
+
+PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}
+
+
+def bench_precision(args):
+    """Precision: N x 7552 features scored against K identities with FP32,
+    BF16, FP16 and FP8-e4m3 operands (FP32 accumulation). The feature rows are
+    the uniform-batch generator's (8192 distinct crops, tiled to N rows: the
+    GEMM's time does not depend on the values). Error and argmax agreement are
+    measured on 2048 rows against an FP64 numpy product."""
+    import torch
+
+    from paper_1504_01883_amd import lbpf, synth
+    torch.cuda.set_device(0)
+    N, K = args.precision_rows, args.precision_identities
+    distinct = min(8192, N)
+    g, z, _ = synth.make_crops(distinct, SIDE, SIDE, synth.W_PRECISION, N_IDENT)
+    ctx = lbpf.Context()
+    D = ctx.dim
+    dg, dz = lbpf.to_device_planes(g.reshape(-1, SIDE), z.reshape(-1, SIDE))
+    base, _ = ctx.features([(dg, dz)], synth.stacked_boxes(distinct, SIDE, SIDE))
+    X = base.repeat((N + distinct - 1) // distinct, 1)[:N].contiguous()
+    del base, dg, dz
+    W, b = synth.synthetic_weights(K, D, synth.W_PRECISION)
+    Wd, bd = torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda()
+    S = torch.empty((N, K), dtype=torch.float32, device="cuda")
+    A = torch.empty((N,), dtype=torch.int32, device="cuda")
+    sample = 2048
+    Xs = X[:sample].double().cpu().numpy()
+    S64 = Xs @ W.astype(np.float64).T + b.astype(np.float64)[None, :]
+    A64 = S64.argmax(axis=1)
+    flops = 2.0 * N * K * D
+    res = {}
+    for prec in ("fp32", "bf16", "fp16", "fp8"):
+        wts = ctx.weights(Wd, bd, precision=prec)
+        steps = max(1, min(args.steps, 3 if prec == "fp32" else 10))
+        ctx.score(X, wts, scores_out=S, argmax_out=A)
+        torch.cuda.synchronize()
+        e = _events(2)
+        e[0].record()
+        for _ in range(steps):
+            ctx.score(X, wts, scores_out=S, argmax_out=A)
+        e[1].record()
+        torch.cuda.synchronize()
+        ms = e[0].elapsed_time(e[1]) / steps
+        tf = flops / (ms * 1e-3) / 1e12
+        Sg = S[:sample].double().cpu().numpy()
+        res[prec] = {"ms": ms, "tflops": tf, "peak_tflops": PEAKS_TFLOPS[prec],
+                     "mfma_frac": tf / PEAKS_TFLOPS[prec],
+                     "max_abs_err_vs_fp64": float(np.abs(Sg - S64).max()),
+                     "argmax_agreement": float((A[:sample].cpu().numpy() == A64).mean()),
+                     "includes": "feature-row quantisation + GEMM + argmax" if prec != "fp32"
+                                 else "GEMM + argmax"}
+        print(f"[bench] {prec}: {ms:.2f} ms, {tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        wts.close()
+    best = max(res, key=lambda k: res[k]["tflops"])
+    out = {"metric": "scoring TFLOP/s by operand precision", "value": res[best]["tflops"],
+           "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": f"precision: {N} x {D} features vs {K} identities",
+                      "rows": N, "identities": K, "dim": D, "flops_per_launch": flops,
+                      "error_sample_rows": sample},
+           "by_precision": res}
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 
