@@ -54,6 +54,8 @@ def _parse():
     p.add_argument("--precision-rows", type=int, default=131072)
     p.add_argument("--precision-identities", type=int, default=8192)
     p.add_argument("--ragged-crops", type=int, default=16384)
+    p.add_argument("--serve-seconds", type=float, default=30.0)
+    p.add_argument("--serve-warmup", type=float, default=2.0)
     return p.parse_args()
 
 

@@ -38,10 +38,13 @@
  *   - lbpf_features / lbpf_features_batch / lbpf_score never allocate device
  *     memory; all scratch is owned by the context and sized at creation.
  *   - A context is used by one host thread at a time; several contexts may
- *     coexist. Work queued on different streams through the same context may
- *     overlap only for lbpf_features_batch and lbpf_score (lbpf_features
- *     stages box tables through a small ring of buffers and waits for the
- *     oldest slot before reusing it).
+ *     coexist. Work may be queued on several streams through one context:
+ *     lbpf_features stages box tables through a small ring of buffers (it
+ *     waits for the oldest slot before reusing it), and lbpf_score calls that
+ *     use the context's scratch (reduced precision, or argmax without caller
+ *     scores) are ordered across streams by an event the context keeps, so
+ *     they never overlap each other; everything else may overlap. Inside a
+ *     captured graph that ordering is the graph's.
  */
 #ifndef LBPF_H
 #define LBPF_H

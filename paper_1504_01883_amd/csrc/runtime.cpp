@@ -54,6 +54,7 @@ struct lbpf_ctx {
     int32_t *d_plain_median = nullptr;  // plain path: one crop's median
     uint32_t *d_plain_counts = nullptr; // plain path: one crop's counts
     std::vector<CropDesc> h_crops;      // host staging of resolved boxes
+    hipEvent_t scratch_ev = nullptr;    // last use of d_scores / d_xq / d_sx
     uint8_t *d_xq = nullptr;            // reduced-precision scoring: quantised feature rows
     float *d_sx = nullptr;              //   and their scales, kLpChunkRows rows
     size_t xq_bytes = 0;
@@ -228,6 +229,8 @@ lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_
     }
     if ((e = hipMalloc((void **)&ctx->d_scores, kScoreScratchElems * sizeof(float))) != hipSuccess)
         return cleanup(fail_hip(e, "hipMalloc"));
+    if ((e = hipEventCreateWithFlags(&ctx->scratch_ev, hipEventDisableTiming)) != hipSuccess)
+        return cleanup(fail_hip(e, "hipEventCreate"));
     if ((e = hipMalloc((void **)&ctx->d_plain_median, sizeof(int32_t))) != hipSuccess)
         return cleanup(fail_hip(e, "hipMalloc"));
     if ((e = hipMalloc((void **)&ctx->d_plain_counts, sizeof(uint32_t) * fp.dim)) != hipSuccess)
@@ -248,6 +251,7 @@ void lbpf_destroy(lbpf_ctx *ctx) {
     if (ctx->d_bins) (void)hipFree(ctx->d_bins);
     if (ctx->d_scores) (void)hipFree(ctx->d_scores);
     if (ctx->d_plain_median) (void)hipFree(ctx->d_plain_median);
+    if (ctx->scratch_ev) (void)hipEventDestroy(ctx->scratch_ev);
     if (ctx->d_xq) (void)hipFree(ctx->d_xq);
     if (ctx->d_sx) (void)hipFree(ctx->d_sx);
     if (ctx->d_plain_counts) (void)hipFree(ctx->d_plain_counts);
@@ -561,6 +565,14 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
     // otherwise as many as the context's score scratch holds.
     int32_t rows = scores_opt ? N : (int32_t)std::max<size_t>(1, ctx->scores_elems / K);
     if (w->prec != LBPF_FP32) rows = std::min(rows, kLpChunkRows);
+    // Calls that use the context's scratch (reduced precision, or argmax
+    // without caller scores) are ordered across streams by scratch_ev. Under
+    // graph capture the graph's own order applies instead.
+    const bool uses_scratch = w->prec != LBPF_FP32 || !scores_opt;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap), "hipStreamIsCapturing");
+    const bool order = uses_scratch && cap == hipStreamCaptureStatusNone;
+    if (order) HIP_TRY(hipStreamWaitEvent(s, ctx->scratch_ev, 0), "hipStreamWaitEvent");
     for (int32_t n0 = 0; n0 < N; n0 += rows) {
         const int32_t n = std::min(rows, N - n0);
         float *S = scores_opt ? scores_opt + (size_t)n0 * K : ctx->d_scores;
@@ -577,6 +589,7 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
         }
         if (argmax_opt) HIP_TRY(launch_argmax(S, n, w->K, argmax_opt + n0, s), "argmax launch");
     }
+    if (order) HIP_TRY(hipEventRecord(ctx->scratch_ev, s), "hipEventRecord");
     return LBPF_OK;
 }
 

@@ -158,3 +158,50 @@ def synthetic_weights(K: int, D: int, workload: int):
     W = rng.standard_normal((K, D), dtype=np.float32)
     b = (0.01 * rng.standard_normal(K)).astype(np.float32)
     return W, b
+
+
+FRAME_W, FRAME_H = 640, 480
+
+
+def make_frame(stream: int, index: int, n_ident: int, workload: int = W_SERVING):
+    """One Kinect-shaped 640x480 frame of stream `stream` with 1-8 faces.
+
+    Returns (grey u8 [480, 640], depth u16 [480, 640], boxes i32 [n, 4] as
+    (x, y, w, h), identities i32 [n]). Box sides are 48-256 px (aspect
+    0.8-1.25), placed without overlap by rejection sampling; each face is a
+    crop from render_crop pasted at its box. The grey background is a smooth
+    gradient plus noise, the depth background a tilted plane in 2500-4000 mm
+    plus noise, with 2% invalid (0) pixels."""
+    rng = np.random.default_rng([SEED, workload, 13_000_001, stream, index])
+    ys = np.arange(FRAME_H, dtype=np.float64)[:, None]
+    xs = np.arange(FRAME_W, dtype=np.float64)[None, :]
+    g0, gx, gy = rng.uniform(60, 180), rng.uniform(-0.1, 0.1), rng.uniform(-0.1, 0.1)
+    grey = np.clip(np.rint(g0 + gx * xs + gy * ys) + rng.integers(-8, 9, size=(FRAME_H, FRAME_W)),
+                   0, 255)
+    z0, zx, zy = rng.uniform(2800, 3700), rng.uniform(-0.6, 0.6), rng.uniform(-0.6, 0.6)
+    depth = np.clip(np.rint(z0 + zx * (xs - 320) + zy * (ys - 240)) +
+                    rng.integers(-5, 6, size=(FRAME_H, FRAME_W)), 2500, 4000)
+    grey = grey.astype(np.uint8)
+    depth = depth.astype(np.uint16)
+    want = int(rng.integers(1, 9))
+    boxes, idents = [], []
+    for _ in range(200):
+        if len(boxes) == want:
+            break
+        w = int(rng.integers(48, 257))
+        h = int(np.clip(np.rint(w * rng.uniform(0.8, 1.25)), 48, 256))
+        h = min(h, FRAME_H)
+        x = int(rng.integers(0, FRAME_W - w + 1))
+        y = int(rng.integers(0, FRAME_H - h + 1))
+        if any(x < bx + bw and bx < x + w and y < by + bh and by < y + h
+               for bx, by, bw, bh in boxes):
+            continue
+        ident = int(rng.integers(0, n_ident))
+        fg, fz = render_crop(w, h, workload, ident, 100_000 + stream * 10_000 + index)
+        grey[y:y + h, x:x + w] = fg
+        depth[y:y + h, x:x + w] = fz
+        boxes.append((x, y, w, h))
+        idents.append(ident)
+    invalid = rng.random((FRAME_H, FRAME_W)) < 0.02
+    depth[invalid] = 0
+    return grey, depth, np.array(boxes, np.int32).reshape(-1, 4), np.array(idents, np.int32)

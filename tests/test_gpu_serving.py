@@ -1,0 +1,76 @@
+"""GPU tests of the serving loop: every frame's result is the same alone and in
+the mix (features and scores row-independent: bitwise), results match the
+oracle, and a tight HBM budget defers admission without losing frames."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1504_01883_amd import lbpf, serve, synth
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+K = 64
+
+
+@pytest.fixture(scope="module")
+def setup():
+    require_gpu()
+    ctx = lbpf.Context()
+    W, b = synth.synthetic_weights(K, ctx.dim, synth.W_SERVING)
+    wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda(), precision="bf16")
+    frames = [synth.make_frame(s, i, K) for s in range(4) for i in range(6)]
+    yield ctx, wts, W, b, frames
+    ctx.close()
+
+
+def _serve(ctx, wts, frames, arrivals, n_slots=32, budget_frames=32, batch=16, inflight=2):
+    be = serve.GpuBackend(ctx, wts, n_slots, batch, inflight=inflight, keep_scores=True)
+    handles = {}
+    for (t, s, i) in arrivals:
+        g, z, bx, ids = frames[i]
+        handles[(s, i)] = (be.host_frame(g, z), bx, ids)
+    sch = serve.Scheduler(n_slots, budget_frames * serve.FRAME_BYTES, max_batch_frames=batch)
+    measured, wall, reqs = serve.run(be, sch, arrivals, handles)
+    return {r.rid: r for r in measured}, sch
+
+
+def test_alone_equals_mix(setup):
+    ctx, wts, W, b, frames = setup
+    mix_arrivals = [(0.0005 * i, i % 4, i) for i in range(len(frames))]
+    mix, _ = _serve(ctx, wts, frames, mix_arrivals)
+    assert len(mix) == len(frames)
+    for i in range(len(frames)):
+        alone, _ = _serve(ctx, wts, frames, [(0.0, 0, i)], batch=1, inflight=1)
+        a = alone[0]
+        m = mix[i]
+        assert np.array_equal(a.argmax, m.argmax)
+        assert np.array_equal(a.scores.view(np.uint32), m.scores.view(np.uint32))
+
+
+def test_serving_matches_oracle(setup, ref):
+    ctx, wts, W, b, frames = setup
+    arrivals = [(0.0, 0, i) for i in range(6)]
+    res, _ = _serve(ctx, wts, frames, arrivals)
+    for i in range(6):
+        g, z, bx, _ = frames[i]
+        boxes = [[0, int(x), int(y), int(w), int(h)] for (x, y, w, h) in bx]
+        f, _, _ = ref.features([(g, z)], boxes, n_threads=8)
+        S64, A64 = ref.score_f64(f, W, b)
+        got = res[i]
+        # BF16 scoring: errors are bounded by the operand rounding; compare the
+        # argmax where the oracle's margin is clear of it.
+        err = np.abs(got.scores - S64).max()
+        assert err < 0.05
+        top2 = np.sort(S64, axis=1)[:, -2:]
+        clear = (top2[:, 1] - top2[:, 0]) > 4 * err
+        assert np.array_equal(got.argmax[clear], A64[clear])
+
+
+def test_tight_budget_defers_but_completes(setup):
+    ctx, wts, W, b, frames = setup
+    arrivals = [(0.0, i % 4, i) for i in range(len(frames))]
+    res, sch = _serve(ctx, wts, frames, arrivals, n_slots=8, budget_frames=2, batch=4)
+    assert sorted(res) == list(range(len(frames)))
+    assert sch.deferrals > 0
+    assert sch.bytes_in_use == 0
