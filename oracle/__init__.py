@@ -16,6 +16,9 @@ the paper it follows:
 * ``uniform_bin``-- uniform patterns of the LBP operator of ref. [16].
 * ``features``   -- Sec. 2.4, Eq. 3 (regional histograms); Sec. 3 (grey u8 and
                     ushort depth).
+* ``features_warped`` -- Sec. 2.1, Eq. 1 (affine frame p' = x u + y v + t)
+                    and Sec. 3 (faces resized to 200 x 200): nearest samples
+                    through a 16.16 fixed-point frame, then ``features``.
 * ``score_f64``  -- Sec. 2.5 (one hyperplane per person; largest score wins).
 * ``train_ovr_f64`` -- Sec. 2.5 (max-margin, one person vs the rest).
 
@@ -63,6 +66,15 @@ class _Box(ctypes.Structure):
                 ("w", ctypes.c_int32), ("h", ctypes.c_int32)]
 
 
+class _Frame(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("ux", "uy", "vx", "vy", "tx", "ty")]
+
+
+class _WarpBox(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_int32), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
+                ("grey", _Frame), ("depth", _Frame)]
+
+
 _lib = None
 
 
@@ -89,6 +101,9 @@ def _load():
         lib.lbpf_ref_codes.argtypes = [vp, i32, vp, i32, i32, i32, i32, vp, vp, vp]
         lib.lbpf_ref_features.restype = i32
         lib.lbpf_ref_features.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, i32]
+        lib.lbpf_ref_features_warped.restype = i32
+        lib.lbpf_ref_features_warped.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp,
+                                                 vp, vp, i32]
         lib.lbpf_ref_score_f64.restype = None
         lib.lbpf_ref_score_f64.argtypes = [vp, i64, vp, vp, i32, i32, vp, vp, i32]
         lib.lbpf_ref_train_ovr_f64.restype = i32
@@ -175,6 +190,43 @@ def features(images, boxes, grid_x=8, grid_y=8, mapping=MAP_U59, window=150,
                                n_threads)
     if rc != 0:
         raise ValueError("oracle: invalid feature arguments (box outside image, side < 3, ...)")
+    return feat, counts, n_in
+
+
+def _images(images, keep):
+    imgs = (_Image * max(1, len(images)))()
+    for i, (g, z) in enumerate(images):
+        z = _c(z, np.uint16)
+        g = _c(g if g is not None else np.zeros_like(z, dtype=np.uint8), np.uint8)
+        keep += [g, z]
+        imgs[i] = _Image(_ptr(g), _ptr(z), z.shape[1], z.shape[0], g.shape[1], z.shape[1])
+    return imgs
+
+
+def features_warped(images, boxes, grid_x=8, grid_y=8, mapping=MAP_U59, window=150,
+                    modality=MOD_BOTH):
+    """Features of warped crops.
+
+    boxes: sequence of (image, w, h, grey_frame, depth_frame) with each frame a
+    6-tuple (ux, uy, vx, vy, tx, ty) in 16.16 fixed point: crop pixel (x, y)
+    samples source (floor((ux x + vx y + tx) / 2^16), floor((uy x + vy y + ty) / 2^16)).
+    Returns (feat f32 [n, D], counts u32 [n, D], n_in i64 [n])."""
+    lib = _load()
+    keep = []
+    imgs = _images(images, keep)
+    n = len(boxes)
+    bx = (_WarpBox * max(1, n))()
+    for i, (im, w, h, gf, zf) in enumerate(boxes):
+        bx[i] = _WarpBox(im, w, h, _Frame(*[int(v) for v in gf]), _Frame(*[int(v) for v in zf]))
+    D = feature_dim(grid_x, grid_y, mapping, modality)
+    feat = np.zeros((n, D), np.float32)
+    counts = np.zeros((n, D), np.uint32)
+    n_in = np.zeros((n,), np.int64)
+    rc = lib.lbpf_ref_features_warped(ctypes.addressof(imgs), len(images), ctypes.addressof(bx),
+                                      n, grid_x, grid_y, mapping, window, modality, _ptr(counts),
+                                      _ptr(feat), _ptr(n_in), 1)
+    if rc != 0:
+        raise ValueError("oracle: invalid warped-feature arguments (sample outside the plane, ...)")
     return feat, counts, n_in
 
 

@@ -23,6 +23,13 @@
  *   lbpf_ref_features      -- Sec. 2.4, Eq. 3: per-region histograms of the
  *                             codes, concatenated; Sec. 3: grey (u8) and
  *                             ushort depth images.
+ *   lbpf_ref_features_warped -- Sec. 2.1, Eq. 1 (p' = x u + y v + t: the
+ *                             affine frame that turns the mapped face region
+ *                             into a rectangle) and Sec. 3 (the face resized to
+ *                             200 x 200): every crop pixel is sampled from its
+ *                             plane through a fixed-point affine frame (nearest
+ *                             sample), then the crop goes through
+ *                             lbpf_ref_features unchanged.
  *   lbpf_ref_score_f64     -- Sec. 2.5: one linear SVM hyperplane per person,
  *                             decision value w.x + b, best score wins.
  *   lbpf_ref_train_ovr_f64 -- Sec. 2.5: max-margin hyperplane, one-vs-rest
@@ -300,6 +307,90 @@ int32_t lbpf_ref_features(const lbpf_ref_image *imgs, int32_t n_img, const lbpf_
     for (int t = 1; t < n_threads; ++t) pthread_join(th[t], NULL);
     free(jobs);
     free(th);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Warped crops (Sec. 2.1, Eq. 1; Sec. 3 resize). A frame maps crop pixel
+ * (x, y) to the source pixel
+ *     sx = floor((ux x + vx y + tx) / 65536),  sy = floor((uy x + vy y + ty) / 65536),
+ * i.e. p' = x u + y v + t with u = (ux, uy), v = (vx, vy), t = (tx, ty) in
+ * 16.16 fixed point, evaluated exactly in 64-bit integers (nearest sample: no
+ * interpolation). Every sample must lie inside its plane. */
+typedef struct {
+    int32_t ux, uy, vx, vy, tx, ty;
+} lbpf_ref_frame;
+
+typedef struct {
+    int32_t image, w, h;
+    lbpf_ref_frame grey, depth;
+} lbpf_ref_warp_box;
+
+static int64_t floor_div65536(int64_t a) {
+    int64_t q = a / 65536;
+    if (a % 65536 != 0 && a < 0) q -= 1; /* C division truncates toward zero */
+    return q;
+}
+
+/* Sample one plane of element size `esz` through frame f into dst (w*h,
+ * pitch w). Returns 0, or -1 if any sample falls outside the plane. */
+static int sample_plane(const void *src, int pitch, int width, int height, int esz,
+                        const lbpf_ref_frame *f, int w, int h, void *dst) {
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            int64_t sx = floor_div65536((int64_t)f->ux * x + (int64_t)f->vx * y + f->tx);
+            int64_t sy = floor_div65536((int64_t)f->uy * x + (int64_t)f->vy * y + f->ty);
+            if (sx < 0 || sy < 0 || sx >= width || sy >= height) return -1;
+            size_t at = (size_t)sy * pitch + (size_t)sx;
+            if (esz == 1)
+                ((uint8_t *)dst)[(size_t)y * w + x] = ((const uint8_t *)src)[at];
+            else
+                ((uint16_t *)dst)[(size_t)y * w + x] = ((const uint16_t *)src)[at];
+        }
+    return 0;
+}
+
+/* Features of every warped crop; the same outputs as lbpf_ref_features.
+ * Returns 0, or -1 for invalid arguments (image index, side outside
+ * 3..1024, a NULL plane the modality needs, a sample outside its plane). */
+int32_t lbpf_ref_features_warped(const lbpf_ref_image *imgs, int32_t n_img,
+                                 const lbpf_ref_warp_box *boxes, int32_t n_boxes, int32_t grid_x,
+                                 int32_t grid_y, int32_t mapping, int32_t window, int32_t modality,
+                                 uint32_t *counts, float *feat, int64_t *n_in, int32_t n_threads) {
+    if (grid_x < 1 || grid_y < 1 || (mapping != REF_MAP_U59 && mapping != REF_MAP_FULL256) ||
+        modality < 0 || modality > 2)
+        return -1;
+    int D = lbpf_ref_feature_dim(grid_x, grid_y, mapping, modality);
+    int use_grey = modality != REF_MOD_DEPTH;
+    for (int i = 0; i < n_boxes; ++i) {
+        const lbpf_ref_warp_box *b = &boxes[i];
+        if (b->image < 0 || b->image >= n_img) return -1;
+        if (b->w < 3 || b->h < 3 || b->w > 1024 || b->h > 1024) return -1;
+        const lbpf_ref_image *im = &imgs[b->image];
+        if (!im->depth || (use_grey && !im->grey)) return -1;
+        uint8_t *g = (uint8_t *)malloc((size_t)b->w * b->h);
+        uint16_t *z = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)b->w * b->h);
+        int bad = sample_plane(im->depth, im->depth_pitch, im->width, im->height, 2, &b->depth,
+                               b->w, b->h, z);
+        if (use_grey && !bad)
+            bad = sample_plane(im->grey, im->grey_pitch, im->width, im->height, 1, &b->grey,
+                               b->w, b->h, g);
+        if (!use_grey) memset(g, 0, (size_t)b->w * b->h);
+        int rc = -1;
+        if (!bad) {
+            /* The sampled crop is an ordinary image: reuse the plain path. */
+            lbpf_ref_image one = {g, z, b->w, b->h, b->w, b->w};
+            lbpf_ref_box whole = {0, 0, 0, b->w, b->h};
+            int64_t n = 0;
+            rc = lbpf_ref_features(&one, 1, &whole, 1, grid_x, grid_y, mapping, window, modality,
+                                   counts + (size_t)i * D, feat + (size_t)i * D, &n, 1);
+            if (n_in) n_in[i] = n;
+        }
+        free(g);
+        free(z);
+        if (rc != 0) return -1;
+    }
+    (void)n_threads; /* one crop at a time: warped sets in the tests are small */
     return 0;
 }
 
