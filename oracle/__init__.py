@@ -19,6 +19,7 @@ the paper it follows:
 * ``features_warped`` -- Sec. 2.1, Eq. 1 (affine frame p' = x u + y v + t)
                     and Sec. 3 (faces resized to 200 x 200): nearest samples
                     through a 16.16 fixed-point frame, then ``features``.
+* ``track``      -- Sec. 2.3, Fig. 4 (nearest box centre in the next frame).
 * ``score_f64``  -- Sec. 2.5 (one hyperplane per person; largest score wins).
 * ``train_ovr_f64`` -- Sec. 2.5 (max-margin, one person vs the rest).
 
@@ -104,6 +105,8 @@ def _load():
         lib.lbpf_ref_features_warped.restype = i32
         lib.lbpf_ref_features_warped.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp,
                                                  vp, vp, i32]
+        lib.lbpf_ref_track.restype = None
+        lib.lbpf_ref_track.argtypes = [vp, vp, i32, vp, vp, i32, i64, vp, vp]
         lib.lbpf_ref_score_f64.restype = None
         lib.lbpf_ref_score_f64.argtypes = [vp, i64, vp, vp, i32, i32, vp, vp, i32]
         lib.lbpf_ref_train_ovr_f64.restype = i32
@@ -235,6 +238,22 @@ def crop_features(grey: np.ndarray, depth: np.ndarray, **kw):
     h, w = np.asarray(depth).shape
     f, c, n = features([(grey, depth)], [[0, 0, 0, w, h]], **kw)
     return f[0], c[0], int(n[0])
+
+
+def track(prev_boxes, prev_stream, cur_boxes, cur_stream, gate2=0):
+    """Nearest-centre association of previous-frame tracks to current boxes.
+    Boxes are [n, 4] (x, y, w, h); streams [n]. Returns (match [P], owner [C])."""
+    pb = _c(np.asarray(prev_boxes).reshape(-1, 4), np.int32)
+    ps = _c(prev_stream, np.int32)
+    cb = _c(np.asarray(cur_boxes).reshape(-1, 4), np.int32)
+    cs = _c(cur_stream, np.int32)
+    P, C = pb.shape[0], cb.shape[0]
+    assert ps.shape == (P,) and cs.shape == (C,)
+    match = np.zeros(P, np.int32)
+    owner = np.zeros(C, np.int32)
+    _load().lbpf_ref_track(_ptr(pb), _ptr(ps), P, _ptr(cb), _ptr(cs), C, int(gate2),
+                           _ptr(match), _ptr(owner))
+    return match, owner
 
 
 def score_f64(X: np.ndarray, W: np.ndarray, b: np.ndarray, want_scores=True, n_threads=1):

@@ -30,6 +30,9 @@
  *                             plane through a fixed-point affine frame (nearest
  *                             sample), then the crop goes through
  *                             lbpf_ref_features unchanged.
+ *   lbpf_ref_track         -- Sec. 2.3 and Fig. 4: a face is followed into the
+ *                             next frame by the detection whose box centre is
+ *                             nearest to its centre in the previous frame.
  *   lbpf_ref_score_f64     -- Sec. 2.5: one linear SVM hyperplane per person,
  *                             decision value w.x + b, best score wins.
  *   lbpf_ref_train_ovr_f64 -- Sec. 2.5: max-margin hyperplane, one-vs-rest
@@ -392,6 +395,50 @@ int32_t lbpf_ref_features_warped(const lbpf_ref_image *imgs, int32_t n_img,
     }
     (void)n_threads; /* one crop at a time: warped sets in the tests are small */
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nearest-centre tracking (Sec. 2.3, Fig. 4). Boxes are (x, y, w, h) int32,
+ * each with a stream id (only boxes of the same stream are compared). The
+ * centre is kept doubled, (2x + w, 2y + h), so it is an exact integer; the
+ * distance is the squared Euclidean distance of doubled centres (int64).
+ *   match[p] = the current box nearest to track p (lowest index on ties), or
+ *              -1 if the stream has none within the gate;
+ *   owner[c] = among the tracks whose match is c, the nearest (lowest track
+ *              index on ties), or -1: c is a new face.
+ * gate2 > 0 limits the distance: a box counts only if the squared distance of
+ * the (undoubled) centres is <= gate2, i.e. doubled distance <= 4 gate2. */
+void lbpf_ref_track(const int32_t *prev, const int32_t *prev_stream, int32_t P,
+                    const int32_t *cur, const int32_t *cur_stream, int32_t C, int64_t gate2,
+                    int32_t *match, int32_t *owner) {
+    int64_t *best_d = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C > 0 ? C : 1));
+    for (int c = 0; c < C; ++c) {
+        owner[c] = -1;
+        best_d[c] = -1;
+    }
+    for (int p = 0; p < P; ++p) {
+        int64_t px = 2 * (int64_t)prev[4 * p] + prev[4 * p + 2];
+        int64_t py = 2 * (int64_t)prev[4 * p + 1] + prev[4 * p + 3];
+        int best = -1;
+        int64_t bd = 0;
+        for (int c = 0; c < C; ++c) {
+            if (cur_stream[c] != prev_stream[p]) continue;
+            int64_t dx = 2 * (int64_t)cur[4 * c] + cur[4 * c + 2] - px;
+            int64_t dy = 2 * (int64_t)cur[4 * c + 1] + cur[4 * c + 3] - py;
+            int64_t d = dx * dx + dy * dy;
+            if (gate2 > 0 && d > 4 * gate2) continue;
+            if (best < 0 || d < bd) {
+                best = c;
+                bd = d;
+            }
+        }
+        match[p] = best;
+        if (best >= 0 && (best_d[best] < 0 || bd < best_d[best])) {
+            best_d[best] = bd; /* p ascending: an equal distance keeps the lower p */
+            owner[best] = p;
+        }
+    }
+    free(best_d);
 }
 
 /* ------------------------------------------------------------------------ */
