@@ -159,6 +159,95 @@ int32_t lbpf_batch_size(const lbpf_batch *batch);
 lbpf_status lbpf_features_batch(lbpf_ctx *ctx, const lbpf_batch *batch, float *hist,
                                 uint32_t *counts_opt, void *stream);
 
+/* Sampling frame of one plane, after Eq. 1 (Sec. 2.1: p' = x u + y v + t, the
+ * affine map that turns the mapped face region into a rectangle), in 16.16
+ * fixed point: crop pixel (x, y) reads the plane pixel
+ *     sx = floor((ux*x + vx*y + tx) / 65536),  sy = floor((uy*x + vy*y + ty) / 65536)
+ * evaluated exactly in 64-bit integers (nearest sample, no interpolation).
+ * The identity frame of box (x0, y0) is {65536, 0, 0, 65536, x0*65536,
+ * y0*65536}; Sec. 3's resize of a w x h box to 200 x 200 is ux = w*65536/200,
+ * vy = h*65536/200 with t offset by half a step. */
+typedef struct lbpf_frame {
+    int32_t ux, uy, vx, vy, tx, ty;
+} lbpf_frame;
+
+/* A warped face crop of w x h pixels (3 <= w, h <= LBPF_MAX_SIDE) sampled from
+ * image `image`: grey through frame `grey` (ignored when the modality has no
+ * grey channel), depth through frame `depth`. Every sample must lie inside
+ * the image (checked on the four corners, which bound an affine map). */
+typedef struct lbpf_warp_box {
+    int32_t image, w, h;
+    lbpf_frame grey, depth;
+} lbpf_warp_box;
+
+/* Device workspace bytes one warped w x h crop occupies (a multiple of 256);
+ * 0 for sides outside 3..LBPF_MAX_SIDE. */
+size_t lbpf_warp_crop_bytes(int32_t w, int32_t h);
+
+/* Features of warped crops: the same outputs as lbpf_features for the crops
+ * the frames sample (steps 1-5 run on the sampled w x h crop). images and
+ * boxes are HOST arrays (planes DEVICE memory); hist / counts_opt are DEVICE
+ * [n_boxes][D]. workspace is caller-owned DEVICE memory (256-byte aligned)
+ * of workspace_bytes, at least lbpf_warp_crop_bytes of the largest crop: the
+ * sampled crops are staged there and the call works through the boxes in
+ * order, in groups whose crops fit it together (one sampling kernel and one
+ * feature kernel per group, all on `stream`). The workspace must not be used
+ * by other work until the call's work on `stream` has finished.
+ * Errors: LBPF_E_INVALID (NULL pointers, bad sides, a sample outside the
+ * image, misaligned or too small workspace), LBPF_E_BUDGET (more than
+ * LBPF_MAX_BOXES_PER_CALL boxes), LBPF_E_HIP. */
+lbpf_status lbpf_features_warped(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                                 const lbpf_warp_box *boxes, int32_t n_boxes, void *workspace,
+                                 size_t workspace_bytes, float *hist, uint32_t *counts_opt,
+                                 void *stream);
+
+/* On-device training of the per-person hyperplanes (Sec. 2.5: max margin,
+ * each person against all others; the paper trains on the CPU, Sec. 3).
+ * For every class k in 0..K-1 (y_i = +1 where labels[i] == k, else -1):
+ * L2-regularised hinge loss with cost C, the bias as an extra constant
+ * feature 1, the features scaled by sigma = 1 / (lower median of the row
+ * norms; 1 if that is 0), solved in FP64 by dual coordinate descent (Hsieh
+ * et al. 2008). Epoch e of class k visits the samples in the Fisher-Yates
+ * order (i = N-1 down to 1 swaps i with r mod (i+1)) drawn from the
+ * splitmix64 stream seeded with seed ^ (k+1) * 0x5851F42D4C957F2D, draws
+ * e(N-1) onwards; it stops after the first epoch whose largest projected
+ * gradient is below eps, or after max_epochs.
+ * X: DEVICE [N][D] FP32 features (D = lbpf_feature_dim, at most 8192);
+ * labels: DEVICE [N] int32; 1 <= N <= 12288, K >= 1, C > 0, eps > 0,
+ * max_epochs >= 1.
+ * Outputs (DEVICE): W [K][D] and b [K] FP32 (sigma w and the bias weight,
+ * rounded to nearest: ready for lbpf_weights_create), W64_opt / b64_opt the
+ * same in FP64 (or NULL), epochs_opt [K] the epochs each class ran (or NULL).
+ * alpha_io: DEVICE [K][N] FP64 dual variables, or NULL; with warm != 0 they
+ * are the starting point (w is rebuilt from them: the incremental update
+ * after new faces are labelled, new rows starting at 0); the final values are
+ * written back whenever alpha_io is given.
+ * workspace: DEVICE, lbpf_train_workspace_bytes(N) bytes, 8-byte aligned.
+ * Errors: LBPF_E_INVALID, LBPF_E_UNSUPPORTED (D or N above the limits),
+ * LBPF_E_HIP. */
+size_t lbpf_train_workspace_bytes(int32_t N);
+lbpf_status lbpf_train_ovr(lbpf_ctx *ctx, const float *X, const int32_t *labels, int32_t N,
+                           int32_t K, double C, double eps, int32_t max_epochs, uint64_t seed,
+                           double *alpha_io, int32_t warm, float *W, float *b, double *W64_opt,
+                           double *b64_opt, int32_t *epochs_opt, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
+/* Nearest-centre tracking (Sec. 2.3, Fig. 4): each face of the previous frame
+ * (a track) is followed by the detection of the same stream whose box centre
+ * is nearest to its previous centre. prev / cur: HOST int32 [P][4] / [C][4]
+ * boxes (x, y, w, h), every value within +-32767 and w, h >= 0; prev_stream /
+ * cur_stream: HOST int32 [P] / [C] stream (camera) ids. Distances are
+ * squared Euclidean distances of the box centres, computed exactly;
+ * gate2 > 0 ignores boxes farther than sqrt(gate2) pixels (<= 0: no gate).
+ * Outputs (DEVICE int32): match [P] = the nearest current box for each track
+ * (lowest index on ties) or -1; owner [C] = among the tracks matched to a box
+ * the nearest one (lowest track index on ties), or -1 for a new face.
+ * P, C <= 16384 (0 allowed). Errors: LBPF_E_INVALID, LBPF_E_BUDGET (sizes),
+ * LBPF_E_HIP. */
+lbpf_status lbpf_track(lbpf_ctx *ctx, const int32_t *prev, const int32_t *prev_stream,
+                       int32_t P, const int32_t *cur, const int32_t *cur_stream, int32_t C,
+                       int64_t gate2, int32_t *match, int32_t *owner, void *stream);
+
 /* Launch shape of the fused feature kernel for one batch. persistent = 0:
  * one workgroup per crop; 1: wg_per_cu workgroups per compute unit take
  * crops from a device work queue (sorted = 1: largest crop first) until it is

@@ -15,7 +15,8 @@ CSRC = PKG / "csrc"
 OBJ = PKG / "_build"
 LIB = PKG / "liblbpf.so"
 
-SOURCES = ["features.hip", "score.hip", "score_lp.hip", "plain.hip", "runtime.cpp", "tables.cpp"]
+SOURCES = ["features.hip", "score.hip", "score_lp.hip", "plain.hip", "warp.hip", "train.hip",
+           "track.hip", "runtime.cpp", "tables.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -523,7 +523,7 @@ __device__ __forceinline__ void load_tables(FastShared &sh, const uint8_t *table
 // Features of one crop by the whole workgroup: row `out` (and `cout` when
 // not null) of length fp.dim. The tables must already be in LDS; the caller
 // separates consecutive crops with a barrier. kPF = rows loaded ahead.
-template <int kPF>
+template <int kPF, bool kEarly>
 __device__ void fast_crop(const CropDesc &c, const FeatParams &fp, FastShared &sh, float *out,
                           uint32_t *cout) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -536,21 +536,34 @@ __device__ void fast_crop(const CropDesc &c, const FeatParams &fp, FastShared &s
     for (int y = tid; y < h; y += kThreads) sh.rowband[y] = (uint8_t)(((y + 1) * gy - 1) / h);
     for (int x = tid; x < w; x += kThreads) sh.colband[x] = (uint8_t)(((x + 1) * gx - 1) / w);
 
+    // Stream geometry of the code phase. Its first rows do not depend on the
+    // median: with kEarly their loads are issued now and land while the
+    // median is computed (at the price of registers held across it).
+    const bool fast = w <= kFastMaxW;
+    const int L = (w + 3) >> 2;           // lanes per stream (<= 64 when fast)
+    const int spw = fast ? 64 / L : 1;    // streams per wave
+    const int sw = lane / L;              // stream of this lane within the wave
+    const int x0 = 4 * (lane - sw * L);
+    const int S = kWaves * spw;
+    const int s = wave * spw + (sw < spw ? sw : 0);
+    const int rows = h - 2;
+    const int yb = 1 + (s * rows) / S;
+    const int ye = (fast && sw < spw) ? 1 + ((s + 1) * rows) / S : yb;
+    const bool full = (c.flags & kCropOverReadOk) || x0 + 4 <= w;
+    RawRow rawA, rawB, ring[kPF];
+    auto prime = [&]() {
+        rawA = load_row(c, yb - 1, x0, full);
+        rawB = load_row(c, yb, x0, full);
+#pragma unroll
+        for (int u = 0; u < kPF; ++u) ring[u] = load_row(c, min(yb + 1 + u, h - 1), x0, full);
+    };
+    if (kEarly && yb < ye) prime();
+
     const int32_t m = crop_median_fast(c, sh.ms, sh.red);  // ends with a barrier
 
-    if (w <= kFastMaxW) {
-        if (m >= 0) {
-            const int L = (w + 3) >> 2;           // lanes per stream (<= 64)
-            const int spw = 64 / L;               // streams per wave
-            const int sw = lane / L;              // stream of this lane within the wave
-            const int x0 = 4 * (lane - sw * L);
-            const int S = kWaves * spw;
-            const int s = wave * spw + (sw < spw ? sw : 0);
-            const int rows = h - 2;
-            const int yb = 1 + (s * rows) / S;
-            const int ye = (sw < spw) ? 1 + ((s + 1) * rows) / S : yb;
-            const bool full = (c.flags & kCropOverReadOk) || x0 + 4 <= w;
-
+    if (fast) {
+        if (m >= 0 && yb < ye) {
+            if (!kEarly) prime();
             const int32_t lo = m - fp.window;
             const uint32_t lolo = (uint32_t)(lo & 0xFFFF) * 0x10001u;
             const uint32_t span2 = (uint32_t)(2 * fp.window) * 0x10001u;
@@ -568,15 +581,8 @@ __device__ void fast_crop(const CropDesc &c, const FeatParams &fp, FastShared &s
             const uint32_t dep4 = (uint32_t)(cells * kU59) * 4u;
             char *hbase = reinterpret_cast<char *>(sh.hist);
 
-            Row6 A, B;
-            if (yb < ye) {
-                A = make_row(load_row(c, yb - 1, x0, full), lo, lolo, span2);
-                B = make_row(load_row(c, yb, x0, full), lo, lolo, span2);
-            }
-            RawRow ring[kPF];
-#pragma unroll
-            for (int u = 0; u < kPF; ++u) ring[u] = load_row(c, min(yb + 1 + u, h - 1), x0, full);
-
+            Row6 A = make_row(rawA, lo, lolo, span2);
+            Row6 B = make_row(rawB, lo, lolo, span2);
             for (int y = yb; y < ye; y += kPF) {
 #pragma unroll
                 for (int u = 0; u < kPF; ++u) {
@@ -650,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
     __shared__ FastShared sh;
     load_tables(sh, tables);
     const size_t i = blockIdx.x;
-    fast_crop<kPF>(crops[i], fp, sh, hist + i * fp.dim, counts ? counts + i * fp.dim : nullptr);
+    fast_crop<kPF, true>(crops[i], fp, sh, hist + i * fp.dim, counts ? counts + i * fp.dim : nullptr);
 }
 
 // Persistent: a fixed grid of workgroups takes crops from a work queue in the
@@ -671,7 +677,7 @@ __global__ __launch_bounds__(kThreads) void k_features_persistent(
         const int32_t j = sh.next;
         if (j >= n) break;  // uniform: every thread read the same j
         const size_t i = order ? (size_t)order[j] : (size_t)j;
-        fast_crop<kPF>(crops[i], fp, sh, hist + i * fp.dim, counts ? counts + i * fp.dim : nullptr);
+        fast_crop<kPF, false>(crops[i], fp, sh, hist + i * fp.dim, counts ? counts + i * fp.dim : nullptr);
         __syncthreads();
     }
     if (threadIdx.x == 0) {

@@ -76,6 +76,43 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
                            const float *sw, const float *b, int32_t K, int32_t D, int32_t mode,
                            float *S, hipStream_t s);
 
+// Warped crops (warp.hip): each crop is sampled from its planes through two
+// 16.16 fixed-point affine frames into a staging crop of pitch w, which the
+// feature kernels then read as an ordinary image. 104 bytes.
+struct WarpDesc {
+    const uint8_t *g_src;   // grey plane at image pixel (0, 0); null if unused
+    const uint16_t *d_src;  // depth plane at image pixel (0, 0)
+    uint8_t *g_dst;         // staging grey crop, w * h bytes, pitch w
+    uint16_t *d_dst;        // staging depth crop, w * h u16, pitch w
+    int32_t g_pitch, d_pitch;
+    int32_t src_w, src_h;   // plane size (samples are clamped into it)
+    int32_t w, h;
+    int32_t gf[6], df[6];   // frames (ux, uy, vx, vy, tx, ty)
+};
+static_assert(sizeof(WarpDesc) == 104, "WarpDesc layout");
+hipError_t launch_warp(const WarpDesc *d, int32_t n, hipStream_t s);
+
+// SVM training (train.hip): one-vs-rest dual coordinate descent in FP64, one
+// workgroup per class. D <= kTrainMaxD, 1 <= N <= kTrainMaxN (alpha and the
+// epoch's order live in LDS). workspace: train_workspace_bytes(N) bytes.
+constexpr int32_t kTrainMaxD = 8192;
+constexpr int32_t kTrainMaxN = 12288;
+size_t train_workspace_bytes(int32_t N);
+hipError_t launch_train(const float *X, const int32_t *labels, int32_t N, int32_t D, int32_t K,
+                        double C, double eps, int32_t max_epochs, uint64_t seed, double *alpha,
+                        int32_t warm, float *W, float *b, double *W64, double *b64,
+                        int32_t *epochs, void *workspace, hipStream_t s);
+
+// Nearest-centre tracking (track.hip). Boxes are int32 (x, y, w, h) with
+// |coordinates| <= kTrackMaxCoord, so doubled-centre distances stay below
+// 2^37 and (distance << 24) | track fits 64 bits; P <= kTrackMaxBoxes.
+// keys: C u64 of scratch.
+constexpr int32_t kTrackMaxCoord = 32767;
+constexpr int32_t kTrackMaxBoxes = 16384;
+hipError_t launch_track(const int32_t *prev, const int32_t *ps, int32_t P, const int32_t *cur,
+                        const int32_t *cs, int32_t C, int64_t gate2, int32_t *match,
+                        int32_t *owner, uint64_t *keys, hipStream_t s);
+
 // Scoring (score.hip).
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b,
                             int32_t K, int32_t D, float *S, hipStream_t s);

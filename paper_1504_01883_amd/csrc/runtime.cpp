@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -590,6 +591,226 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
         if (argmax_opt) HIP_TRY(launch_argmax(S, n, w->K, argmax_opt + n0, s), "argmax launch");
     }
     if (order) HIP_TRY(hipEventRecord(ctx->scratch_ev, s), "hipEventRecord");
+    return LBPF_OK;
+}
+
+size_t lbpf_warp_crop_bytes(int32_t w, int32_t h) {
+    if (w < 3 || h < 3 || w > LBPF_MAX_SIDE || h > LBPF_MAX_SIDE) return 0;
+    const size_t px = (size_t)w * (size_t)h;
+    // Each plane keeps kOverRead elements of slack past its last row, so the
+    // feature kernels' row loads may run past the right edge.
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    return up(px + 2 * kOverRead) + up(2 * px + 4 * kOverRead);
+}
+
+lbpf_status lbpf_features_warped(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
+                                 const lbpf_warp_box *boxes, int32_t n_boxes, void *workspace,
+                                 size_t workspace_bytes, float *hist, uint32_t *counts_opt,
+                                 void *stream) {
+    if (!ctx) return fail(LBPF_E_INVALID, "ctx is NULL");
+    if (n_boxes < 0 || n_images < 0) return fail(LBPF_E_INVALID, "negative count");
+    if (n_boxes > LBPF_MAX_BOXES_PER_CALL)
+        return fail(LBPF_E_BUDGET, "more boxes than LBPF_MAX_BOXES_PER_CALL");
+    if (n_boxes == 0) return LBPF_OK;
+    if (!boxes || !images || n_images == 0 || !hist)
+        return fail(LBPF_E_INVALID, "NULL image table, box table or hist");
+    if (!workspace || ((uintptr_t)workspace & 255u))
+        return fail(LBPF_E_INVALID, "workspace is NULL or not 256-byte aligned");
+    const bool grey = ctx->fp.use_grey != 0;
+    // Range of one sampled coordinate over the crop: an affine function takes
+    // its extremes at the corners and floor is monotone, so the corner
+    // samples bound every sample.
+    auto range = [](int32_t a, int32_t b, int32_t t, int32_t w, int32_t h, int64_t &lo,
+                    int64_t &hi) {
+        lo = INT64_MAX;
+        hi = INT64_MIN;
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                const int64_t v = ((int64_t)a * (cx ? w - 1 : 0) + (int64_t)b * (cy ? h - 1 : 0) +
+                                   t) >> 16;
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+    };
+    size_t largest = 0;
+    for (int32_t i = 0; i < n_boxes; ++i) {
+        const lbpf_warp_box &b = boxes[i];
+        char buf[200];
+        if (b.image < 0 || b.image >= n_images) {
+            snprintf(buf, sizeof buf, "warped box %d: image index %d out of range", i, b.image);
+            return fail(LBPF_E_INVALID, buf);
+        }
+        const lbpf_image &im = images[b.image];
+        if (!im.depth || (grey && !im.grey) || im.width < 1 || im.height < 1 ||
+            im.depth_pitch < im.width || (grey && im.grey_pitch < im.width)) {
+            snprintf(buf, sizeof buf, "warped box %d: image %d has a NULL plane or a bad size", i,
+                     b.image);
+            return fail(LBPF_E_INVALID, buf);
+        }
+        const size_t cb = lbpf_warp_crop_bytes(b.w, b.h);
+        if (cb == 0) {
+            snprintf(buf, sizeof buf, "warped box %d: side %dx%d outside 3..%d", i, b.w, b.h,
+                     LBPF_MAX_SIDE);
+            return fail(LBPF_E_INVALID, buf);
+        }
+        largest = std::max(largest, cb);
+        for (int p = 0; p < (grey ? 2 : 1); ++p) {
+            const lbpf_frame &f = p == 0 ? b.depth : b.grey;
+            int64_t x0, x1, y0, y1;
+            range(f.ux, f.vx, f.tx, b.w, b.h, x0, x1);
+            range(f.uy, f.vy, f.ty, b.w, b.h, y0, y1);
+            if (x0 < 0 || y0 < 0 || x1 >= im.width || y1 >= im.height) {
+                snprintf(buf, sizeof buf,
+                         "warped box %d: %s samples x %lld..%lld, y %lld..%lld leave the %dx%d image",
+                         i, p == 0 ? "depth" : "grey", (long long)x0, (long long)x1,
+                         (long long)y0, (long long)y1, im.width, im.height);
+                return fail(LBPF_E_INVALID, buf);
+            }
+        }
+    }
+    if (workspace_bytes < largest)
+        return fail(LBPF_E_INVALID, "workspace smaller than the largest warped crop");
+
+    hipStream_t s = (hipStream_t)stream;
+    const size_t D = (size_t)ctx->fp.dim;
+    const size_t slot_bytes = sizeof(CropDesc) * LBPF_MAX_BOXES_PER_CALL;
+    const int32_t max_group = (int32_t)((slot_bytes - 256) / (sizeof(CropDesc) + sizeof(WarpDesc)));
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    int32_t first = 0;
+    while (first < n_boxes) {
+        // The group: boxes first .. last-1 whose crops fit the workspace.
+        int32_t last = first;
+        size_t used = 0;
+        while (last < n_boxes && last - first < max_group) {
+            const size_t cb = lbpf_warp_crop_bytes(boxes[last].w, boxes[last].h);
+            if (used + cb > workspace_bytes) break;
+            used += cb;
+            ++last;
+        }
+        const int32_t n = last - first;
+        const int slot = ctx->ring_next;
+        ctx->ring_next = (slot + 1) % kRing;
+        HIP_TRY(hipEventSynchronize(ctx->ev[slot]), "hipEventSynchronize");
+        uint8_t *h = reinterpret_cast<uint8_t *>(ctx->h_stage[slot]);
+        uint8_t *d = reinterpret_cast<uint8_t *>(ctx->d_stage[slot]);
+        CropDesc *hc = reinterpret_cast<CropDesc *>(h);
+        const size_t woff = (sizeof(CropDesc) * (size_t)n + 255) / 256 * 256;
+        WarpDesc *hw = reinterpret_cast<WarpDesc *>(h + woff);
+        size_t off = 0;
+        for (int32_t j = 0; j < n; ++j) {
+            const lbpf_warp_box &b = boxes[first + j];
+            const lbpf_image &im = images[b.image];
+            const size_t px = (size_t)b.w * (size_t)b.h;
+            uint8_t *g_dst = ws + off;
+            uint16_t *d_dst = reinterpret_cast<uint16_t *>(
+                ws + off + (px + 2 * kOverRead + 255) / 256 * 256);
+            off += lbpf_warp_crop_bytes(b.w, b.h);
+            WarpDesc &wd = hw[j];
+            wd.g_src = grey ? im.grey : nullptr;
+            wd.d_src = im.depth;
+            wd.g_dst = g_dst;
+            wd.d_dst = d_dst;
+            wd.g_pitch = im.grey_pitch;
+            wd.d_pitch = im.depth_pitch;
+            wd.src_w = im.width;
+            wd.src_h = im.height;
+            wd.w = b.w;
+            wd.h = b.h;
+            const lbpf_frame fr[2] = {b.grey, b.depth};
+            for (int p = 0; p < 2; ++p) {
+                int32_t *o = p == 0 ? wd.gf : wd.df;
+                o[0] = fr[p].ux; o[1] = fr[p].uy; o[2] = fr[p].vx;
+                o[3] = fr[p].vy; o[4] = fr[p].tx; o[5] = fr[p].ty;
+            }
+            CropDesc &c = hc[j];
+            c.grey = grey ? g_dst : nullptr;
+            c.depth = d_dst;
+            c.grey_pitch = b.w;
+            c.depth_pitch = b.w;
+            c.w = (int16_t)b.w;
+            c.h = (int16_t)b.h;
+            c.flags = kCropOverReadOk;
+        }
+        HIP_TRY(hipMemcpyAsync(d, h, woff + sizeof(WarpDesc) * (size_t)n, hipMemcpyHostToDevice, s),
+                "hipMemcpyAsync");
+        HIP_TRY(launch_warp(reinterpret_cast<const WarpDesc *>(d + woff), n, s), "warp kernel launch");
+        HIP_TRY(launch_features(reinterpret_cast<const CropDesc *>(d), n, ctx->fp, ctx->d_bins,
+                                hist + (size_t)first * D,
+                                counts_opt ? counts_opt + (size_t)first * D : nullptr, s),
+                "feature kernel launch");
+        HIP_TRY(hipEventRecord(ctx->ev[slot], s), "hipEventRecord");
+        first = last;
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_track(lbpf_ctx *ctx, const int32_t *prev, const int32_t *prev_stream,
+                       int32_t P, const int32_t *cur, const int32_t *cur_stream, int32_t C,
+                       int64_t gate2, int32_t *match, int32_t *owner, void *stream) {
+    if (!ctx) return fail(LBPF_E_INVALID, "ctx is NULL");
+    if (P < 0 || C < 0) return fail(LBPF_E_INVALID, "negative count");
+    if (P > kTrackMaxBoxes || C > kTrackMaxBoxes)
+        return fail(LBPF_E_BUDGET, "more than 16384 tracks or boxes");
+    if ((P > 0 && (!prev || !prev_stream || !match)) || (C > 0 && (!cur || !cur_stream || !owner)))
+        return fail(LBPF_E_INVALID, "NULL box, stream or output array");
+    auto ok = [](const int32_t *b, int32_t n) {
+        for (int64_t i = 0; i < 4 * (int64_t)n; ++i) {
+            if (b[i] < -kTrackMaxCoord || b[i] > kTrackMaxCoord) return false;
+            if ((i & 3) >= 2 && b[i] < 0) return false;
+        }
+        return true;
+    };
+    if (!ok(prev, P) || !ok(cur, C))
+        return fail(LBPF_E_INVALID, "box values must lie within +-32767 with w, h >= 0");
+    if (gate2 > ((int64_t)1 << 36)) gate2 = 0;  // wider than any distance: no gate
+    if (P == 0 && C == 0) return LBPF_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int slot = ctx->ring_next;
+    ctx->ring_next = (slot + 1) % kRing;
+    HIP_TRY(hipEventSynchronize(ctx->ev[slot]), "hipEventSynchronize");
+    // Slot layout: prev [P][4], prev_stream [P], cur [C][4], cur_stream [C],
+    // then 256-byte aligned u64 keys [C] (device only).
+    uint8_t *h = reinterpret_cast<uint8_t *>(ctx->h_stage[slot]);
+    uint8_t *d = reinterpret_cast<uint8_t *>(ctx->d_stage[slot]);
+    const size_t o_ps = 16 * (size_t)P, o_cur = o_ps + 4 * (size_t)P, o_cs = o_cur + 16 * (size_t)C;
+    const size_t bytes = o_cs + 4 * (size_t)C;
+    const size_t o_keys = (bytes + 255) / 256 * 256;
+    std::memcpy(h, prev, 16 * (size_t)P);
+    std::memcpy(h + o_ps, prev_stream, 4 * (size_t)P);
+    std::memcpy(h + o_cur, cur, 16 * (size_t)C);
+    std::memcpy(h + o_cs, cur_stream, 4 * (size_t)C);
+    HIP_TRY(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    HIP_TRY(launch_track(reinterpret_cast<const int32_t *>(d), reinterpret_cast<const int32_t *>(d + o_ps),
+                         P, reinterpret_cast<const int32_t *>(d + o_cur),
+                         reinterpret_cast<const int32_t *>(d + o_cs), C, gate2, match, owner,
+                         reinterpret_cast<uint64_t *>(d + o_keys), s),
+            "tracking kernel launch");
+    HIP_TRY(hipEventRecord(ctx->ev[slot], s), "hipEventRecord");
+    return LBPF_OK;
+}
+
+size_t lbpf_train_workspace_bytes(int32_t N) { return N > 0 ? train_workspace_bytes(N) : 0; }
+
+lbpf_status lbpf_train_ovr(lbpf_ctx *ctx, const float *X, const int32_t *labels, int32_t N,
+                           int32_t K, double C, double eps, int32_t max_epochs, uint64_t seed,
+                           double *alpha_io, int32_t warm, float *W, float *b, double *W64_opt,
+                           double *b64_opt, int32_t *epochs_opt, void *workspace,
+                           size_t workspace_bytes, void *stream) {
+    if (!ctx) return fail(LBPF_E_INVALID, "ctx is NULL");
+    if (!X || !labels || !W || !b || !workspace)
+        return fail(LBPF_E_INVALID, "NULL X, labels, W, b or workspace");
+    if (N < 1 || K < 1) return fail(LBPF_E_INVALID, "N and K must be >= 1");
+    if (!(C > 0.0) || !(eps > 0.0) || max_epochs < 1)
+        return fail(LBPF_E_INVALID, "C and eps must be > 0 and max_epochs >= 1");
+    if (warm && !alpha_io) return fail(LBPF_E_INVALID, "warm start without alpha_io");
+    if ((uintptr_t)workspace & 7u) return fail(LBPF_E_INVALID, "workspace not 8-byte aligned");
+    if (workspace_bytes < train_workspace_bytes(N))
+        return fail(LBPF_E_INVALID, "workspace smaller than lbpf_train_workspace_bytes(N)");
+    if (ctx->fp.dim > kTrainMaxD || N > kTrainMaxN)
+        return fail(LBPF_E_UNSUPPORTED, "training supports D <= 8192 and N <= 12288");
+    HIP_TRY(launch_train(X, labels, N, ctx->fp.dim, K, C, eps, max_epochs, seed, alpha_io, warm,
+                         W, b, W64_opt, b64_opt, epochs_opt, workspace, (hipStream_t)stream),
+            "training kernel launch");
     return LBPF_OK;
 }
 

@@ -35,6 +35,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kTM = 256, kTN = 128;  // workgroup tile
 constexpr int kRowB = 128;           // bytes of k per stage and row
 constexpr int kPitch = 144;          // LDS row pitch (bytes)
+constexpr uint32_t kGroupN = 4;      // row tiles per group of the tile order
 
 // --- conversions ------------------------------------------------------------
 
@@ -151,7 +152,18 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
     __shared__ __attribute__((aligned(16))) uint8_t sB[kTN * kPitch];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int32_t n0 = blockIdx.x * kTM, k0 = blockIdx.y * kTN;
+    // Tile order. Consecutive workgroups are dealt round-robin to the 8 XCDs;
+    // the remap gives each XCD a contiguous range of logical tiles, walked in
+    // groups of kGroupN row tiles x all identity tiles, so the ~32 tiles an XCD
+    // runs at once share 4 feature-row tiles and 8 weight tiles in its L2.
+    const uint32_t nwg = gridDim.x, pid = blockIdx.x;
+    const uint32_t xcd = pid & 7u, per = nwg >> 3, rem = nwg & 7u;
+    const uint32_t L = xcd * per + min(xcd, rem) + (pid >> 3);
+    const uint32_t KT = (uint32_t)(K + kTN - 1) / kTN, NT = (uint32_t)(N + kTM - 1) / kTM;
+    const uint32_t g = L / (kGroupN * KT), i_g = L - g * (kGroupN * KT);
+    const uint32_t gn = min((uint32_t)kGroupN, NT - g * kGroupN);
+    const int32_t n0 = (int32_t)(g * kGroupN + i_g % gn) * kTM;
+    const int32_t k0 = (int32_t)(i_g / gn) * kTN;
 
     // Global -> register staging: thread t moves 16-byte chunk (t % 8) of rows
     // t / 8 + 32 j.
@@ -272,7 +284,7 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
                            float *S, hipStream_t s) {
     if (N <= 0 || K <= 0) return hipSuccess;
     const int32_t pitch = lp_pitch(D, mode);
-    dim3 grid((N + kTM - 1) / kTM, (K + kTN - 1) / kTN);
+    dim3 grid(((K + kTN - 1) / kTN) * ((N + kTM - 1) / kTM));
     if (mode == LBPF_BF16)
         hipLaunchKernelGGL(k_score_lp<LBPF_BF16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,
                            pitch, S);

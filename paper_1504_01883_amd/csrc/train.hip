@@ -1,0 +1,263 @@
+// On-device SVM training (Sec. 2.5: one max-margin hyperplane per person, that
+// person against all others; the paper trains on the CPU, Sec. 3).
+//
+// Problem per class k: L2-regularised hinge loss with C, the bias as an extra
+// constant feature 1, features scaled by sigma = 1 / (lower median of the
+// sample norms). Solver: dual coordinate descent (Hsieh et al., ICML 2008),
+// in FP64, visiting the samples of every epoch in a seeded random order:
+//   G  = y_i w.x_i - 1
+//   PG = G, except min(G, 0) at alpha_i = 0 and max(G, 0) at alpha_i = C
+//   alpha_i <- clamp(alpha_i - G / Q_ii, 0, C), Q_ii = x_i.x_i (+1 for the bias)
+//   w <- w + (alpha_i' - alpha_i) y_i x_i
+// until max |PG| over an epoch is below eps, or max_epochs. W = sigma w, b =
+// the bias weight.
+//
+// Order of the samples: epoch e of class k is a Fisher-Yates shuffle of
+// 0..N-1 (i from N-1 down to 1 swaps i with r mod (i+1)) drawing r from the
+// splitmix64 stream (Steele, Lea and Flood, OOPSLA 2014: state += golden
+// gamma, output = the variant-13 mix of the state) seeded with
+// seed XOR (k+1) * 0x5851F42D4C957F2D; epoch e uses draws e(N-1) .. e(N-1)+N-2
+// (splitmix64 is counter based: draw m is the mix of state0 + (m+1) gamma).
+// One thread shuffles while the others wait at the barrier; it costs a few
+// percent of an epoch.
+//
+// Layout: one workgroup per class. Thread t owns coordinates d = t + 256 j
+// (j < kJ) of w, held in registers; the sample row is read as FP32 straight
+// from the feature matrix (coalesced, one row ahead), scaled in FP64. alpha
+// and the epoch's order live in LDS. One barrier per coordinate step (the
+// dot product's cross-wave sum, double-buffered).
+#include "lbpf_internal.h"
+
+namespace lbpf {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Squared norms of the rows (one wave per row) and, with sigma given, the
+// diagonal Q_ii = sum (sigma x)^2 + 1.
+__global__ __launch_bounds__(kThreads) void k_row_norms(const float *__restrict__ X, int32_t N,
+                                                        int32_t D, const double *__restrict__ sigma,
+                                                        double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int32_t i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (i >= N) return;
+    const float *x = X + (size_t)i * D;
+    const double s = sigma ? *sigma : 1.0;
+    double acc = 0.0;
+    for (int d = lane; d < D; d += 64) {
+        const double v = s * (double)x[d];
+        acc += v * v;
+    }
+    acc = wave_sum_f64(acc);
+    if (lane == 0) out[i] = sigma ? acc + 1.0 : sqrt(acc);
+}
+
+// sigma = 1 / (lower median of the norms), 1 when that median is 0: the
+// element of rank (N-1)/2, ranks broken by index so exactly one qualifies.
+__global__ __launch_bounds__(kThreads) void k_sigma(const double *__restrict__ norms, int32_t N,
+                                                    double *__restrict__ sigma) {
+    const uint32_t want = (uint32_t)(N - 1) / 2;
+    for (int32_t i = threadIdx.x; i < N; i += kThreads) {
+        const double v = norms[i];
+        uint32_t rank = 0;
+        for (int32_t j = 0; j < N; ++j) {
+            const double u = norms[j];
+            rank += (u < v || (u == v && j < i)) ? 1u : 0u;
+        }
+        if (rank == want) *sigma = v > 0.0 ? 1.0 / v : 1.0;
+    }
+}
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t state0, uint64_t m) {
+    // Output of draw m (0-based) of a stream whose state starts at state0.
+    uint64_t z = state0 + (m + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct TrainArgs {
+    const float *X;
+    const int32_t *labels;
+    const double *sigma, *qii;
+    int32_t N, D, K;
+    double C, eps;
+    int32_t max_epochs;
+    uint64_t seed;
+    int32_t warm;
+    double *alpha;   // [K][N]: warm start in, final values out (may be null)
+    float *W;        // [K][D]
+    float *b;        // [K]
+    double *W64;     // [K][D] or null
+    double *b64;     // [K] or null
+    int32_t *epochs; // [K] or null
+};
+
+template <int kJ>
+__device__ __forceinline__ void load_row(const float *__restrict__ X, int32_t i, int32_t D, int tid,
+                                         float (&x)[kJ]) {
+    const float *row = X + (size_t)i * D;
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        const int d = tid + kThreads * j;
+        x[j] = d < D ? row[d] : 0.0f;
+    }
+}
+
+// One workgroup per class. Dynamic LDS: alpha (N doubles), order (N ints).
+template <int kJ>
+__global__ __launch_bounds__(kThreads) void k_train(TrainArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    double *alpha = reinterpret_cast<double *>(smem);
+    int32_t *order = reinterpret_cast<int32_t *>(alpha + a.N);
+    __shared__ double red[2][kWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int32_t k = blockIdx.x;
+    const int32_t N = a.N, D = a.D;
+    const double sigma = *a.sigma, C = a.C;
+    const bool warm = a.warm && a.alpha;
+
+    // w: coordinates tid + 256 j in registers; the bias weight wb is kept
+    // by every thread (its updates are uniform).
+    double w[kJ];
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) w[j] = 0.0;
+    double wb = 0.0;
+    for (int32_t i = tid; i < N; i += kThreads) alpha[i] = warm ? a.alpha[(size_t)k * N + i] : 0.0;
+    __syncthreads();
+    if (warm) {
+        // w = sum_i alpha_i y_i x_i over the scaled, augmented samples.
+        for (int32_t i = 0; i < N; ++i) {
+            const double ai = alpha[i];
+            if (ai == 0.0) continue;
+            const double ay = a.labels[i] == k ? ai : -ai;
+            float x[kJ];
+            load_row<kJ>(a.X, i, D, tid, x);
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) w[j] += ay * (sigma * (double)x[j]);
+            wb += ay;
+        }
+    }
+
+    const uint64_t state0 = a.seed ^ (0x5851F42D4C957F2Dull * (uint64_t)(k + 1));
+    int32_t epoch = 0;
+    while (epoch < a.max_epochs) {
+        if (tid == 0) {
+            const uint64_t base = (uint64_t)epoch * (uint64_t)(N - 1);
+            for (int32_t i = 0; i < N; ++i) order[i] = i;
+            for (int32_t i = N - 1; i > 0; --i) {
+                const uint64_t r = splitmix64_at(state0, base + (uint64_t)(N - 1 - i));
+                const int32_t j = (int32_t)(r % (uint64_t)(i + 1));
+                const int32_t t = order[i];
+                order[i] = order[j];
+                order[j] = t;
+            }
+        }
+        __syncthreads();
+
+        double max_pg = 0.0;
+        float xn[kJ];
+        load_row<kJ>(a.X, order[0], D, tid, xn);
+        for (int32_t s = 0; s < N; ++s) {
+            const int32_t i = order[s];
+            float xc[kJ];
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) xc[j] = xn[j];
+            if (s + 1 < N) load_row<kJ>(a.X, order[s + 1], D, tid, xn);
+            const double a_old = alpha[i];  // read before this step's barrier
+            const double y = a.labels[i] == k ? 1.0 : -1.0;
+            const double q = a.qii[i];
+            double part = 0.0;
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) part += w[j] * (sigma * (double)xc[j]);
+            part = wave_sum_f64(part);
+            if (lane == 0) red[s & 1][wave] = part;
+            __syncthreads();
+            double wx = red[s & 1][0];
+#pragma unroll
+            for (int v = 1; v < kWaves; ++v) wx += red[s & 1][v];
+            wx += wb;
+            const double G = y * wx - 1.0;
+            double PG = G;
+            if (a_old <= 0.0) PG = G < 0.0 ? G : 0.0;
+            else if (a_old >= C) PG = G > 0.0 ? G : 0.0;
+            max_pg = fmax(max_pg, fabs(PG));
+            if (PG != 0.0 && q > 0.0) {
+                const double a_new = fmin(fmax(a_old - G / q, 0.0), C);
+                if (tid == 0) alpha[i] = a_new;
+                const double step = (a_new - a_old) * y;
+                if (step != 0.0) {
+#pragma unroll
+                    for (int j = 0; j < kJ; ++j) w[j] += step * (sigma * (double)xc[j]);
+                    wb += step;
+                }
+            }
+        }
+        ++epoch;
+        __syncthreads();  // order and alpha are rewritten next
+        if (max_pg < a.eps) break;  // uniform: every thread holds the same max_pg
+    }
+
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        const int d = tid + kThreads * j;
+        if (d < D) {
+            const double v = sigma * w[j];
+            a.W[(size_t)k * D + d] = (float)v;
+            if (a.W64) a.W64[(size_t)k * D + d] = v;
+        }
+    }
+    if (tid == 0) {
+        a.b[k] = (float)wb;
+        if (a.b64) a.b64[k] = wb;
+        if (a.epochs) a.epochs[k] = epoch;
+    }
+    if (a.alpha)
+        for (int32_t i = tid; i < N; i += kThreads) a.alpha[(size_t)k * N + i] = alpha[i];
+}
+
+template <int kJ>
+hipError_t launch_train_j(const TrainArgs &a, hipStream_t s) {
+    const size_t lds = (size_t)a.N * (sizeof(double) + sizeof(int32_t));
+    hipError_t e = hipFuncSetAttribute((const void *)k_train<kJ>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_train<kJ>, dim3(a.K), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t train_workspace_bytes(int32_t N) { return ((size_t)2 * N + 1) * sizeof(double); }
+
+hipError_t launch_train(const float *X, const int32_t *labels, int32_t N, int32_t D, int32_t K,
+                        double C, double eps, int32_t max_epochs, uint64_t seed, double *alpha,
+                        int32_t warm, float *W, float *b, double *W64, double *b64,
+                        int32_t *epochs, void *workspace, hipStream_t s) {
+    double *norms = static_cast<double *>(workspace);
+    double *qii = norms + N;
+    double *sigma = qii + N;
+    const dim3 rows((N + kWaves - 1) / kWaves);
+    hipLaunchKernelGGL(k_row_norms, rows, dim3(kThreads), 0, s, X, N, D, nullptr, norms);
+    hipLaunchKernelGGL(k_sigma, dim3(1), dim3(kThreads), 0, s, norms, N, sigma);
+    hipLaunchKernelGGL(k_row_norms, rows, dim3(kThreads), 0, s, X, N, D, sigma, qii);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    TrainArgs a{X, labels, sigma, qii, N, D, K, C, eps, max_epochs, seed, warm, alpha,
+                W, b, W64, b64, epochs};
+    if (D <= 4 * kThreads) return launch_train_j<4>(a, s);
+    if (D <= 8 * kThreads) return launch_train_j<8>(a, s);
+    if (D <= 16 * kThreads) return launch_train_j<16>(a, s);
+    return launch_train_j<32>(a, s);
+}
+
+}  // namespace lbpf

@@ -31,7 +31,8 @@ EXPORTS = [
     "lbpf_weights_create", "lbpf_weights_destroy", "lbpf_weights_count", "lbpf_score",
     "lbpf_debug_codes", "lbpf_status_string", "lbpf_last_error", "lbpf_features_plain",
     "lbpf_score_plain", "lbpf_batch_set_launch", "lbpf_batch_get_launch", "lbpf_tune_batch",
-    "lbpf_graph_create", "lbpf_graph_launch", "lbpf_graph_destroy",
+    "lbpf_graph_create", "lbpf_graph_launch", "lbpf_graph_destroy", "lbpf_warp_crop_bytes",
+    "lbpf_features_warped", "lbpf_train_workspace_bytes", "lbpf_train_ovr", "lbpf_track",
 ]
 
 
@@ -50,6 +51,32 @@ class Image(ctypes.Structure):
 class Box(ctypes.Structure):
     _fields_ = [("image", ctypes.c_int32), ("x", ctypes.c_int32), ("y", ctypes.c_int32),
                 ("w", ctypes.c_int32), ("h", ctypes.c_int32)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("ux", "uy", "vx", "vy", "tx", "ty")]
+
+
+class WarpBox(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_int32), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
+                ("grey", Frame), ("depth", Frame)]
+
+
+ONE = 1 << 16  # 1.0 in the frames' 16.16 fixed point
+
+
+def box_frame(x: int, y: int) -> tuple:
+    """The identity frame of a box whose top-left pixel is (x, y)."""
+    return (ONE, 0, 0, ONE, x * ONE, y * ONE)
+
+
+def resize_frame(x: int, y: int, w: int, h: int, out_w: int, out_h: int) -> tuple:
+    """Nearest-sample resize of box (x, y, w, h) to out_w x out_h, sampling at
+    the centre of each output pixel: step w/out_w (16.16, rounded down) and
+    half a step of offset."""
+    ux = (w * ONE) // out_w
+    vy = (h * ONE) // out_h
+    return (ux, 0, 0, vy, x * ONE + ux // 2, y * ONE + vy // 2)
 
 
 class LaunchCfg(ctypes.Structure):
@@ -103,6 +130,12 @@ def load():
         "lbpf_graph_create": (st, [vp, vp, vp, vp, vp, vp, vp]),
         "lbpf_graph_launch": (st, [vp, vp]),
         "lbpf_graph_destroy": (None, [vp]),
+        "lbpf_warp_crop_bytes": (sz, [i32, i32]),
+        "lbpf_features_warped": (st, [vp, vp, i32, vp, i32, vp, sz, vp, vp, vp]),
+        "lbpf_train_workspace_bytes": (sz, [i32]),
+        "lbpf_train_ovr": (st, [vp, vp, vp, i32, i32, ctypes.c_double, ctypes.c_double, i32,
+                                ctypes.c_uint64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lbpf_track": (st, [vp, vp, vp, i32, vp, vp, i32, ctypes.c_int64, vp, vp, vp]),
         "lbpf_status_string": (ctypes.c_char_p, [st]),
         "lbpf_last_error": (ctypes.c_char_p, []),
     }
@@ -286,6 +319,74 @@ class Context:
         _check(load().lbpf_features(self._h, imgs, len(planes), bx, n, _dptr(hist),
                                     _dptr(cnt), _stream()))
         return hist, cnt
+
+    def features_warped(self, planes, boxes, with_counts=False, out=None, workspace=None):
+        """Features of warped crops. boxes: [(image, w, h, grey_frame, depth_frame)]
+        with frames as 6-tuples (see box_frame / resize_frame). workspace: a
+        uint8 CUDA tensor (256-byte aligned); default: one sized for every crop."""
+        imgs = make_images(planes)
+        n = len(boxes)
+        arr = (WarpBox * max(1, n))()
+        for i, (im, w, h, gf, zf) in enumerate(boxes):
+            arr[i] = WarpBox(im, w, h, Frame(*[int(v) for v in gf]), Frame(*[int(v) for v in zf]))
+        dev = planes[0][1].device if planes else torch.device("cuda")
+        if workspace is None:
+            total = sum(int(load().lbpf_warp_crop_bytes(w, h)) for (_, w, h, _, _) in boxes)
+            workspace = torch.empty(max(total, 256), dtype=torch.uint8, device=dev)
+        hist = out if out is not None else torch.empty((n, self.dim), dtype=torch.float32,
+                                                       device=dev)
+        cnt = torch.empty((n, self.dim), dtype=torch.int32, device=dev) if with_counts else None
+        _check(load().lbpf_features_warped(self._h, imgs, len(planes), arr, n, _dptr(workspace),
+                                           workspace.numel(), _dptr(hist), _dptr(cnt), _stream()))
+        return hist, cnt
+
+    def train(self, X: torch.Tensor, labels: torch.Tensor, K: int, C=1.0, eps=1e-3,
+              max_epochs=200, seed=150401883, alpha=None, warm=False, want_f64=False):
+        """One-vs-rest SVM training on the device -> dict with W, b (FP32) and
+        epochs [K]; W64 / b64 with want_f64; alpha (FP64 [K, N]) is updated in
+        place when given (warm=True starts from it)."""
+        if X.dim() != 2 or X.dtype != torch.float32 or not X.is_contiguous():
+            raise ValueError("X must be a contiguous FP32 [N, D] tensor")
+        if X.shape[1] != self.dim:
+            raise ValueError(f"X has {X.shape[1]} columns, the context's feature dim is {self.dim}")
+        N = X.shape[0]
+        lab = labels.to(device=X.device, dtype=torch.int32).contiguous()
+        dev = X.device
+        W = torch.empty((K, self.dim), dtype=torch.float32, device=dev)
+        b = torch.empty((K,), dtype=torch.float32, device=dev)
+        W64 = torch.empty((K, self.dim), dtype=torch.float64, device=dev) if want_f64 else None
+        b64 = torch.empty((K,), dtype=torch.float64, device=dev) if want_f64 else None
+        ep = torch.empty((K,), dtype=torch.int32, device=dev)
+        if alpha is not None and (alpha.dtype != torch.float64 or tuple(alpha.shape) != (K, N)
+                                  or not alpha.is_contiguous()):
+            raise ValueError("alpha must be a contiguous FP64 [K, N] tensor")
+        nbytes = int(load().lbpf_train_workspace_bytes(N))
+        ws = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=dev)
+        _check(load().lbpf_train_ovr(self._h, _dptr(X), _dptr(lab), N, K, float(C), float(eps),
+                                     int(max_epochs), int(seed), _dptr(alpha), int(bool(warm)),
+                                     _dptr(W), _dptr(b), _dptr(W64), _dptr(b64), _dptr(ep),
+                                     _dptr(ws), ws.numel(), _stream()))
+        out = {"W": W, "b": b, "epochs": ep, "workspace": ws}
+        if want_f64:
+            out["W64"], out["b64"] = W64, b64
+        return out
+
+    def track(self, prev_boxes, prev_stream, cur_boxes, cur_stream, gate2=0, device="cuda"):
+        """Nearest-centre tracking: host box arrays ([n, 4] (x, y, w, h), streams
+        [n]) -> (match [P], owner [C]) int32 device tensors."""
+        pb = np.ascontiguousarray(np.asarray(prev_boxes, np.int32).reshape(-1, 4))
+        cb = np.ascontiguousarray(np.asarray(cur_boxes, np.int32).reshape(-1, 4))
+        ps = np.ascontiguousarray(np.asarray(prev_stream, np.int32).reshape(-1))
+        cs = np.ascontiguousarray(np.asarray(cur_stream, np.int32).reshape(-1))
+        if ps.shape[0] != pb.shape[0] or cs.shape[0] != cb.shape[0]:
+            raise ValueError("one stream id per box")
+        match = torch.empty(pb.shape[0], dtype=torch.int32, device=device)
+        owner = torch.empty(cb.shape[0], dtype=torch.int32, device=device)
+        _check(load().lbpf_track(self._h, pb.ctypes.data, ps.ctypes.data, pb.shape[0],
+                                 cb.ctypes.data, cs.ctypes.data, cb.shape[0], int(gate2),
+                                 _dptr(match) if match.numel() else None,
+                                 _dptr(owner) if owner.numel() else None, _stream()))
+        return match, owner
 
     def features_plain(self, planes, boxes, with_counts=False, out=None):
         """The plain unbatched comparator path (same results, per-crop launches)."""

@@ -71,3 +71,37 @@ def test_null_arguments_rejected_without_device_work(lib):
     lib.lbpf_create.restype = ctypes.c_int
     lib.lbpf_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     assert lib.lbpf_create(None, None, 0) == -1
+
+
+def test_warp_crop_bytes(lib):
+    lib.lbpf_warp_crop_bytes.restype = ctypes.c_size_t
+    lib.lbpf_warp_crop_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    for w, h in [(3, 3), (200, 200), (255, 97), (1024, 1024)]:
+        b = lib.lbpf_warp_crop_bytes(w, h)
+        assert b % 256 == 0
+        assert b >= 3 * w * h + 3 * 7  # both planes plus the row over-read slack
+    for w, h in [(2, 5), (5, 2), (1025, 5), (5, 1025), (-1, 5)]:
+        assert lib.lbpf_warp_crop_bytes(w, h) == 0
+    lib.lbpf_features_warped.restype = ctypes.c_int
+    lib.lbpf_features_warped.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]
+    assert lib.lbpf_features_warped(None, None, 0, None, 0, None, 0, None, None, None) == -1
+
+
+@pytest.mark.parametrize("w", [48, 97, 128, 199, 200, 201, 256, 640])
+def test_resize_frame_samples_stay_in_the_box(w):
+    """Host helper: the corner samples of a resize frame land on the box's
+    first and last pixel in both axes (by linearity, every sample is inside)."""
+    from paper_1504_01883_amd import lbpf
+    x0, y0, h = 13, 7, int(w * 1.1)
+    for out in (200, 64, 3, 1024):
+        ux, uy, vx, vy, tx, ty = lbpf.resize_frame(x0, y0, w, h, out, out)
+        sx = lambda x: (ux * x + tx) >> 16
+        sy = lambda y: (vy * y + ty) >> 16
+        assert uy == 0 and vx == 0
+        assert x0 <= sx(0) and sx(out - 1) <= x0 + w - 1
+        assert y0 <= sy(0) and sy(out - 1) <= y0 + h - 1
+        if out == w:
+            assert [sx(x) for x in range(out)] == list(range(x0, x0 + w))
