@@ -14,7 +14,10 @@ classify loop, Sec. 3, Fig. 10, run for many cameras at once). The server
   next batch (continuous batching), with up to `inflight` batches on
   different compute streams at once;
 * retires batches when their completion event fires, frees their slots and
-  records each frame's latency (completion seen by the host minus arrival).
+  records each frame's latency (completion seen by the host minus arrival);
+* optionally tracks faces across each stream's frames (Sec. 2.3: nearest box
+  centre): the association runs on the device inside the batch, and track
+  ids are handed out on the host in each stream's arrival order (TrackBook).
 
 The Scheduler is pure host logic (tested on the CPU with a stand-in backend);
 GpuBackend drives liblbpf through the binding. The "plain" backend processes
@@ -43,6 +46,43 @@ class Request:
     t_done: float = 0.0
     argmax: np.ndarray | None = None
     scores: np.ndarray | None = None
+    prev: "Request | None" = None     # previous frame of the same stream (tracking)
+    owner: np.ndarray | None = None   # per box: index of the previous box it continues, or -1
+    track_ids: np.ndarray | None = None
+    prev_off: int = 0                 # where the previous frame's boxes sit in the device call
+
+
+class TrackBook:
+    """Track ids from the device's association. Each frame's `owner` array
+    (per current box: the index of the previous frame's box whose track it
+    continues, or -1) may arrive in any order across batches; a frame gets its
+    ids once its own owner and its predecessor's ids are known, so every
+    stream resolves in arrival order. New faces get fresh ids."""
+
+    def __init__(self):
+        self.next_id = 0
+        self.pending: dict[int, collections.deque] = {}
+
+    def add(self, req: Request):
+        self.pending.setdefault(req.stream, collections.deque()).append(req)
+
+    def resolve(self) -> int:
+        n = 0
+        for q in self.pending.values():
+            while q and q[0].owner is not None and (q[0].prev is None or
+                                                    q[0].prev.track_ids is not None):
+                req = q.popleft()
+                ids = np.empty(len(req.owner), np.int64)
+                for c, o in enumerate(req.owner):
+                    if o >= 0:
+                        ids[c] = req.prev.track_ids[o]
+                    else:
+                        ids[c] = self.next_id
+                        self.next_id += 1
+                req.track_ids = ids
+                req.prev = None  # only the latest frame of a stream is needed
+                n += 1
+        return n
 
 
 class Scheduler:
@@ -98,10 +138,13 @@ class GpuBackend:
     """Batched features + scores through liblbpf (fused path)."""
 
     def __init__(self, ctx, weights, n_slots: int, max_batch_frames: int, inflight: int = 2,
-                 keep_scores: bool = False, plain: bool = False):
+                 keep_scores: bool = False, plain: bool = False, track: bool = False):
         import torch
         self.torch = torch
         self.ctx, self.weights, self.plain = ctx, weights, plain
+        self.track = track
+        self.book = TrackBook()
+        self.last_req: dict[int, Request] = {}
         self.K = weights.K
         self.keep_scores = keep_scores
         dev = torch.device("cuda")
@@ -118,6 +161,7 @@ class GpuBackend:
                 "S": torch.empty((max_boxes, self.K), dtype=torch.float32, device=dev),
                 "A": torch.empty((max_boxes,), dtype=torch.int32, device=dev),
                 "A_host": torch.empty((max_boxes,), dtype=torch.int32).pin_memory(),
+                "O_host": torch.empty((max_boxes,), dtype=torch.int32).pin_memory(),
                 "S_host": (torch.empty((max_boxes, self.K), dtype=torch.float32).pin_memory()
                            if keep_scores else None),
                 "done": torch.cuda.Event(), "batch": None, "nb": 0})
@@ -164,11 +208,35 @@ class GpuBackend:
                 self.ctx.features(planes, boxes, out=st["hist"][:nb])
                 self.ctx.score(st["hist"][:nb], self.weights, scores_out=st["S"][:nb],
                                argmax_out=st["A"][:nb])
+            if self.track:
+                self._associate(batch, st, nb)
             st["A_host"][:nb].copy_(st["A"][:nb], non_blocking=True)
             if self.keep_scores:
                 st["S_host"][:nb].copy_(st["S"][:nb], non_blocking=True)
             st["done"].record(s)
         st["batch"], st["nb"] = batch, nb
+
+    def _associate(self, batch: list[Request], st, nb: int):
+        """Nearest-centre association of every frame in the batch with the
+        previous frame of its stream (launched earlier, possibly in this
+        batch), as one device call; pair i is frame i of the batch."""
+        prev_boxes, prev_pair, cur_pair = [], [], []
+        off = 0
+        for i, req in enumerate(batch):
+            req.prev = self.last_req.get(req.stream)
+            self.last_req[req.stream] = req
+            self.book.add(req)
+            req.prev_off = off
+            if req.prev is not None:
+                prev_boxes.append(np.asarray(req.prev.boxes, np.int32).reshape(-1, 4))
+                prev_pair.append(np.full(len(req.prev.boxes), i, np.int32))
+                off += len(req.prev.boxes)
+            cur_pair.append(np.full(len(req.boxes), i, np.int32))
+        pb = np.concatenate(prev_boxes) if prev_boxes else np.zeros((0, 4), np.int32)
+        pp = np.concatenate(prev_pair) if prev_pair else np.zeros(0, np.int32)
+        cb = np.concatenate([np.asarray(r.boxes, np.int32).reshape(-1, 4) for r in batch])
+        _, owner = self.ctx.track(pb, pp, cb, np.concatenate(cur_pair))
+        st["O_host"][:nb].copy_(owner, non_blocking=True)
 
     def poll(self) -> list[list[Request]]:
         done = []
@@ -177,16 +245,22 @@ class GpuBackend:
                 t = time.perf_counter()
                 A = st["A_host"][:st["nb"]].numpy().copy()
                 S = st["S_host"][:st["nb"]].numpy().copy() if self.keep_scores else None
+                O = st["O_host"][:st["nb"]].numpy().copy() if self.track else None
                 pos = 0
                 for req in st["batch"]:
                     n = len(req.boxes)
                     req.argmax = A[pos:pos + n]
                     req.scores = S[pos:pos + n] if S is not None else None
+                    if O is not None:  # owners index the call's track list
+                        o = O[pos:pos + n]
+                        req.owner = np.where(o >= 0, o - req.prev_off, -1)
                     req.t_done = t
                     pos += n
                 done.append(st["batch"])
                 st["batch"] = None
                 self.free_sets.append(si)
+        if self.track and done:
+            self.book.resolve()
         return done
 
     def busy(self) -> bool:
@@ -288,9 +362,10 @@ def bench(args) -> dict:
             handles[(s, i)] = cache[key]
         return handles
 
-    def one(rate_mult, plain=False, duration=secs, warmup=warm):
+    def one(rate_mult, plain=False, duration=secs, warmup=warm, track=False):
         arr = poisson_arrivals(n_streams, fps * rate_mult, warmup + duration, synth.SEED)
-        be = GpuBackend(ctx, w_fp32 if plain else w_bf16, n_slots, 64, inflight=2, plain=plain)
+        be = GpuBackend(ctx, w_fp32 if plain else w_bf16, n_slots, 64, inflight=2, plain=plain,
+                        track=track)
         frames = frames_for(be, arr)
         sch = Scheduler(n_slots, budget, max_batch_frames=64)
         measured, wall, _ = run(be, sch, arr, frames, warmup)
@@ -299,6 +374,7 @@ def bench(args) -> dict:
         return out
 
     fused = one(1.0)
+    tracked = one(1.0, duration=min(secs, 10.0), track=True)
     plain = one(1.0, plain=True, duration=min(secs, 10.0))
     sweep = []
     for mult in (4.0, 16.0, 64.0):
@@ -319,6 +395,7 @@ def bench(args) -> dict:
                                    f"{secs:.0f} s measured, {n_slots} frame slots, budget "
                                    f"{budget} B", "streams": n_streams, "fps": fps,
                        "identities": K},
-            "fused": fused, "plain_unbatched_fp32": plain, "saturation_sweep": sweep,
+            "fused": fused, "fused_with_tracking": tracked,
+            "plain_unbatched_fp32": plain, "saturation_sweep": sweep,
             "max_crops_per_s_with_p99_under_frame_interval":
                 sat["crops_per_s"] if sat else None}

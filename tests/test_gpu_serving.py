@@ -24,8 +24,10 @@ def setup():
     ctx.close()
 
 
-def _serve(ctx, wts, frames, arrivals, n_slots=32, budget_frames=32, batch=16, inflight=2):
-    be = serve.GpuBackend(ctx, wts, n_slots, batch, inflight=inflight, keep_scores=True)
+def _serve(ctx, wts, frames, arrivals, n_slots=32, budget_frames=32, batch=16, inflight=2,
+           track=False):
+    be = serve.GpuBackend(ctx, wts, n_slots, batch, inflight=inflight, keep_scores=True,
+                          track=track)
     handles = {}
     for (t, s, i) in arrivals:
         g, z, bx, ids = frames[i]
@@ -33,6 +35,39 @@ def _serve(ctx, wts, frames, arrivals, n_slots=32, budget_frames=32, batch=16, i
     sch = serve.Scheduler(n_slots, budget_frames * serve.FRAME_BYTES, max_batch_frames=batch)
     measured, wall, reqs = serve.run(be, sch, arrivals, handles)
     return {r.rid: r for r in measured}, sch
+
+
+def test_tracking_in_the_serving_loop(setup, ref):
+    """Sec. 2.3 inside the loop: every frame's association with the previous
+    frame of its stream equals the oracle's, and track ids follow it (a
+    continued box keeps its predecessor's id, new faces get unused ids)."""
+    ctx, wts, W, b, frames = setup
+    # frames[i] is stream i // 6, frame i % 6; interleave the four streams.
+    arrivals = [(0.0003 * k, i // 6, i) for k, i in
+                enumerate(sorted(range(len(frames)), key=lambda i: (i % 6, i // 6)))]
+    res, _ = _serve(ctx, wts, frames, arrivals, batch=5, track=True)
+    by_stream = {}
+    for k, (_, st, i) in enumerate(arrivals):
+        by_stream.setdefault(st, []).append((k, i))
+    seen = set()
+    for st, seq in by_stream.items():
+        prev_ids, prev_boxes = None, None
+        for k, i in seq:
+            r = res[k]
+            boxes = frames[i][2]
+            if prev_boxes is None:
+                want = np.full(len(boxes), -1)
+            else:
+                _, want = ref.track(prev_boxes, np.zeros(len(prev_boxes)), boxes,
+                                    np.zeros(len(boxes)))
+            assert r.owner.tolist() == want.tolist()
+            for c, o in enumerate(r.owner):
+                if o >= 0:
+                    assert r.track_ids[c] == prev_ids[o]
+                else:
+                    assert r.track_ids[c] not in seen
+                    seen.add(int(r.track_ids[c]))
+            prev_ids, prev_boxes = r.track_ids, boxes
 
 
 def test_alone_equals_mix(setup):

@@ -105,3 +105,34 @@ def test_poisson_arrivals_rate_and_order():
     assert 0.85 * 4800 < len(arr) < 1.15 * 4800
     per = np.bincount([a[1] for a in arr], minlength=16)
     assert (per > 200).all()
+
+
+def _treq(rid, stream, prev, owner):
+    r = serve.Request(rid=rid, stream=stream, t_arrival=0.0,
+                      boxes=np.zeros((len(owner), 4), np.int32))
+    r.prev = prev
+    r._owner = np.asarray(owner, np.int64)
+    return r
+
+
+def test_trackbook_resolves_in_stream_order():
+    """Results arrive out of order; ids still follow each stream's frames: a
+    box continuing box o of the previous frame inherits o's id, new faces get
+    fresh ids in resolution order."""
+    book = serve.TrackBook()
+    a0 = _treq(0, 0, None, [-1, -1])          # stream 0: two new faces
+    b0 = _treq(1, 1, None, [-1])              # stream 1: one new face
+    a1 = _treq(2, 0, a0, [1, -1, 0])          # continues a0's 1 and 0, one new
+    a2 = _treq(3, 0, a1, [2])                 # continues a1's box 2
+    for r in (a0, b0, a1, a2):
+        book.add(r)
+    for r in (a2, a1):                        # later frames finish first
+        r.owner = r._owner
+    assert book.resolve() == 0 and a2.track_ids is None
+    b0.owner = b0._owner
+    assert book.resolve() == 1 and b0.track_ids.tolist() == [0]
+    a0.owner = a0._owner
+    assert book.resolve() == 3
+    assert a0.track_ids.tolist() == [1, 2]
+    assert a1.track_ids.tolist() == [2, 3, 1]
+    assert a2.track_ids.tolist() == [1]
