@@ -251,7 +251,7 @@ lbpf_status lbpf_track(lbpf_ctx *ctx, const int32_t *prev, const int32_t *prev_s
 /* Launch shape of the fused feature kernel for one batch. persistent = 0:
  * one workgroup per crop; 1: wg_per_cu workgroups per compute unit take
  * crops from a device work queue (sorted = 1: largest crop first) until it is
- * empty. row_prefetch (2 or 4) is how many rows ahead each lane loads. The
+ * empty. row_prefetch (2, 4 or 8) is how many rows ahead each lane loads. The
  * outputs do not depend on the launch shape. */
 typedef struct lbpf_launch_cfg {
     int32_t persistent;

@@ -768,22 +768,25 @@ hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &f
                            uint32_t *queue, int32_t num_cus) {
     if (n <= 0) return hipSuccess;
     if (fast_path_ok(fp)) {
-        const bool pf2 = lc.row_prefetch <= 2;
+        const int pf = lc.row_prefetch <= 2 ? 2 : (lc.row_prefetch <= 4 ? 4 : 8);
         if (lc.persistent && queue) {
             const int grid = std::min<int>(n, std::max(1, lc.wg_per_cu) * num_cus);
             const int32_t *ord = lc.sorted ? order : nullptr;
-            if (pf2)
-                hipLaunchKernelGGL(k_features_persistent<2>, dim3(grid), dim3(kThreads), 0, s,
-                                   crops, ord, n, fp, d_tables, hist, counts, queue);
-            else
-                hipLaunchKernelGGL(k_features_persistent<4>, dim3(grid), dim3(kThreads), 0, s,
-                                   crops, ord, n, fp, d_tables, hist, counts, queue);
-        } else if (pf2) {
-            hipLaunchKernelGGL(k_features_fast<2>, dim3(n), dim3(kThreads), 0, s, crops, fp,
-                               d_tables, hist, counts);
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, crops, ord, n, fp,
+                                   d_tables, hist, counts, queue);
+            };
+            if (pf == 2) go(k_features_persistent<2>);
+            else if (pf == 4) go(k_features_persistent<4>);
+            else go(k_features_persistent<8>);
         } else {
-            hipLaunchKernelGGL(k_features_fast<4>, dim3(n), dim3(kThreads), 0, s, crops, fp,
-                               d_tables, hist, counts);
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(n), dim3(kThreads), 0, s, crops, fp, d_tables, hist,
+                                   counts);
+            };
+            if (pf == 2) go(k_features_fast<2>);
+            else if (pf == 4) go(k_features_fast<4>);
+            else go(k_features_fast<8>);
         }
         return hipGetLastError();
     }

@@ -45,7 +45,7 @@ bool fast_path_ok(const FeatParams &fp);
 struct LaunchCfg {
     int32_t persistent = 0;    // 0: one workgroup per crop; 1: persistent work queue
     int32_t wg_per_cu = 4;     // persistent grid = wg_per_cu * CUs
-    int32_t row_prefetch = 4;  // rows loaded ahead by each lane (2 or 4)
+    int32_t row_prefetch = 4;  // rows loaded ahead by each lane (2, 4 or 8)
     int32_t sorted = 1;        // persistent: take crops largest first
 };
 

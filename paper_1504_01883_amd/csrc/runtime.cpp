@@ -356,7 +356,7 @@ lbpf_status lbpf_features_batch(lbpf_ctx *ctx, const lbpf_batch *batch, float *h
 
 static bool launch_cfg_valid(const lbpf_launch_cfg &c) {
     return (c.persistent == 0 || c.persistent == 1) && c.wg_per_cu >= 1 && c.wg_per_cu <= 16 &&
-           (c.row_prefetch == 2 || c.row_prefetch == 4) && (c.sorted == 0 || c.sorted == 1);
+           (c.row_prefetch == 2 || c.row_prefetch == 4 || c.row_prefetch == 8) && (c.sorted == 0 || c.sorted == 1);
 }
 
 lbpf_status lbpf_batch_set_launch(lbpf_batch *batch, const lbpf_launch_cfg *cfg) {
@@ -381,7 +381,7 @@ lbpf_status lbpf_tune_batch(lbpf_ctx *ctx, lbpf_batch *batch, float *hist, int32
     if (batch->ctx != ctx) return fail(LBPF_E_INVALID, "batch belongs to another context");
     hipStream_t s = (hipStream_t)stream;
     std::vector<lbpf_launch_cfg> cands;
-    for (int pf : {2, 4}) cands.push_back({0, 4, pf, 1});
+    for (int pf : {2, 4, 8}) cands.push_back({0, 4, pf, 1});
     for (int m : {2, 3, 4})
         for (int pf : {2, 4})
             for (int so : {0, 1}) cands.push_back({1, m, pf, so});

@@ -162,6 +162,144 @@ __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ S, int
     if (lane == 0) out[n] = arg;
 }
 
+// --- FP32, LDS ring --------------------------------------------------------------
+//
+// For D a multiple of 32 and 16-byte aligned operands. A workgroup of 8 waves
+// owns a 64 x 64 tile of S; waves 0-3 take the first half of the feature
+// dimension and waves 4-7 the second (two waves per SIMD), and wave t of a
+// half computes the 32 x 32 block (rows 32 (t & 1), columns 32 (t >> 1)) with
+// v_mfma_f32_32x32x2f32 (lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32];
+// D: register r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32).
+// Each half streams 64-byte slices of its 64 X rows and 64 W rows through a
+// ring of kRing LDS stages with global_load_lds_dwordx4 (wave t copies 32 rows
+// of X (t < 2) or W (t >= 2), two 1 KB instructions per stage), issued
+// kRing - 1 stages ahead. Chunk c (16 bytes) of row r sits at position
+// c ^ ((r >> 1) & 3) of the row so that fragment reads of 8 consecutive rows
+// hit 8 bank groups. A lane reads a 16-byte chunk (4 consecutive d) of its
+// row and feeds its components to 4 MFMAs: step s pairs d = 4 q + s of lanes
+// with l / 32 = q, so every d of the slice is used once by both operands.
+// At the end the second half's blocks go through LDS and are added to the
+// first half's in a fixed order, then the bias.
+
+constexpr int kRing = 8;
+constexpr int kSliceB = 64;                        // bytes per row and stage
+constexpr int kHalfStage = 2 * 64 * kSliceB;       // X rows then W rows: 8 KB
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void glb_void_t;
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int kVm>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(kVm >= 0 && kVm < 64, "vmcnt range");
+    // gfx9 s_waitcnt: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8], vmcnt[15:14].
+    __builtin_amdgcn_s_waitcnt((kVm & 15) | (7 << 4) | (15 << 8) | ((kVm >> 4) << 14));
+}
+
+// Wait until at most 2 * `younger` of this wave's copies are in flight.
+__device__ __forceinline__ void wait_stage(int younger) {
+    switch (younger) {
+        case 0: wait_vm<0>(); break;
+        case 1: wait_vm<2>(); break;
+        case 2: wait_vm<4>(); break;
+        case 3: wait_vm<6>(); break;
+        case 4: wait_vm<8>(); break;
+        case 5: wait_vm<10>(); break;
+        default: wait_vm<12>(); break;
+    }
+}
+
+// Barrier that orders LDS only: this wave's LDS reads have returned
+// (lgkmcnt 0) before it arrives. __syncthreads would also drain the copies of
+// the stages still in flight.
+__device__ __forceinline__ void barrier_lds() {
+    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ int fswz(int row, int chunk) { return chunk ^ ((row >> 1) & 3); }
+
+__global__ __launch_bounds__(512) void k_score_f32_ring(const float *__restrict__ X, int32_t N,
+                                                        const float *__restrict__ W,
+                                                        const float *__restrict__ bias,
+                                                        int32_t K, int32_t D,
+                                                        float *__restrict__ S) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * kRing * kHalfStage];  // 128 KB
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = wave >> 2, t = wave & 3;
+    const int32_t n0 = blockIdx.x * kTile, k0 = blockIdx.y * kTile;
+    const int32_t dh = D / 2;
+    const int nst = dh / (kSliceB / 4);
+    uint8_t *ring = lds + half * kRing * kHalfStage;
+
+    // Copy role: 32 rows of X (t < 2) or W (t >= 2); lane i -> row i / 4 of
+    // each 16-row kilobyte, position i % 4.
+    const bool isx = t < 2;
+    const float *mat = isx ? X : W;
+    const int32_t lim = isx ? N : K, base = isx ? n0 : k0;
+    const int rr = lane >> 2, pos = lane & 3;
+    const float *src[2];
+    int dst_off[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int row = (t & 1) * 32 + j * 16 + rr;  // 0..63 within X or W
+        const int32_t g = min(base + row, lim - 1);
+        src[j] = mat + (size_t)g * D + (size_t)half * dh + 4 * fswz(row, pos);
+        dst_off[j] = (isx ? 0 : 64 * kSliceB) + ((t & 1) * 32 + j * 16) * kSliceB;
+    }
+    auto copy = [&](int st) {
+        uint8_t *stage = ring + (st % kRing) * kHalfStage;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            __builtin_amdgcn_global_load_lds((glb_void_t *)(src[j] + st * (kSliceB / 4)),
+                                             (lds_void_t *)(stage + dst_off[j]), 16, 0, 0);
+    };
+
+    const int fr = lane & 31, fq = lane >> 5;
+    const int ra = (t & 1) * 32 + fr, rb = (t >> 1) * 32 + fr;
+    floatx16 acc = {};
+#pragma unroll
+    for (int st = 0; st < kRing - 1; ++st)
+        if (st < nst) copy(st);
+    for (int st = 0; st < nst; ++st) {
+        wait_stage(min(nst - 1 - st, kRing - 2));
+        barrier_lds();
+        if (st + kRing - 1 < nst) copy(st + kRing - 1);
+        const uint8_t *stage = ring + (st % kRing) * kHalfStage;
+#pragma unroll
+        for (int c = 0; c < kSliceB / 32; ++c) {  // two 16-d chunks per lane pair
+            const int ch = 2 * c + fq;
+            const floatx4 a = *reinterpret_cast<const floatx4 *>(stage + ra * kSliceB + 16 * fswz(ra, ch));
+            const floatx4 b = *reinterpret_cast<const floatx4 *>(stage + 64 * kSliceB + rb * kSliceB +
+                                                                 16 * fswz(rb, ch));
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+        }
+    }
+
+    // Second half -> LDS -> added to the first half's block.
+    __syncthreads();
+    floatx16 *part = reinterpret_cast<floatx16 *>(lds);
+    if (half == 1) part[t * 64 + lane] = acc;
+    __syncthreads();
+    if (half == 0) {
+        const floatx16 o = part[t * 64 + lane];
+        const int32_t k = k0 + (t >> 1) * 32 + (lane & 31);
+        if (k < K) {
+            const float bk = bias[k];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int32_t n = n0 + (t & 1) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (n < N) S[(size_t)n * K + k] = (acc[r] + o[r]) + bk;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b, int32_t K,
@@ -169,6 +307,10 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
     if (N <= 0 || K <= 0) return hipSuccess;
     dim3 grid((N + kTile - 1) / kTile, (K + kTile - 1) / kTile);
     const bool vec = (D % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
+    if (vec && D % 32 == 0) {
+        hipLaunchKernelGGL(k_score_f32_ring, grid, dim3(512), 0, s, X, N, W, b, K, D, S);
+        return hipGetLastError();
+    }
     if (vec)
         hipLaunchKernelGGL(k_score_f32<true>, grid, dim3(512), 0, s, X, N, W, b, K, D, S);
     else

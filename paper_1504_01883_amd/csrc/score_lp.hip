@@ -256,6 +256,169 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
     }
 }
 
+// --- GEMM, large tiles ----------------------------------------------------------
+//
+// A workgroup of 4 waves owns a 256 (n) x 256 (k) tile of S; wave (wm, wn)
+// owns rows 128 wm .. +128 and columns 128 wn .. +128 as 4 x 4 blocks of
+// 32 x 32. The reduction dimension advances in stages of 64 bytes per row
+// through a ring of kStages LDS buffers (32 KB each: A 256 rows, B 256 rows).
+// Stages are copied with global_load_lds_dwordx4 (global -> LDS without
+// registers): each wave instruction fills 1 KB = 16 rows of 64 bytes, lane i
+// landing at byte 16 i, so lane i fetches the 16-byte chunk that belongs at
+// row i / 4, position i % 4. Within a row the four chunks are stored at
+// position chunk ^ ((row >> 1) & 3): the 16-byte fragment reads of 8
+// consecutive rows then hit 8 different bank groups.
+// The copy of stage s + kStages - 1 is issued right after the barrier that
+// opens stage s, so kStages - 1 stages are in flight while one is multiplied.
+
+constexpr int kBigT = 256;      // tile rows and columns
+constexpr int kStageB = 64;     // bytes of the reduction per row and stage
+constexpr int kStages = 4;
+constexpr int kStageBytes = 2 * kBigT * kStageB;  // A then B
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void glb_void_t;
+
+template <int kVm>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(kVm >= 0 && kVm < 64, "vmcnt range");
+    // gfx9 s_waitcnt: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8], vmcnt[15:14].
+    __builtin_amdgcn_s_waitcnt((kVm & 15) | (7 << 4) | (15 << 8) | ((kVm >> 4) << 14));
+}
+
+__device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 1) & 3); }
+
+// Workgroup barrier ordering LDS accesses only. __syncthreads would also
+// drain every outstanding global access, including the LDS copies of the
+// stages still in flight, which is exactly the overlap this kernel is after;
+// each wave waits for its own copies of the current stage (wait_vm) first.
+__device__ __forceinline__ void barrier_lds() {
+    // lgkmcnt(0): this wave's LDS reads of the previous stage are done.
+    __builtin_amdgcn_s_waitcnt((63 & 15) | (7 << 4) | (0 << 8) | ((63 >> 4) << 14));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Copy stage kb (byte offset into every row) into LDS buffer `buf`.
+// Rows past the matrix end re-read its last row (their results are dropped).
+__device__ __forceinline__ void copy_stage(const uint8_t *__restrict__ Xq, int32_t N, int32_t n0,
+                                           const uint8_t *__restrict__ Wq, int32_t K, int32_t k0,
+                                           int32_t pitch, int32_t kb, uint8_t *buf, int wave,
+                                           int lane) {
+    const int r_in = lane >> 2, pos = lane & 3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = (wave * 4 + j) * 16 + r_in;  // 0..255
+        const int c = swz(r, pos);
+        const int32_t n = min(n0 + r, N - 1);
+        const uint8_t *src = Xq + (size_t)n * pitch + kb + 16 * c;
+        __builtin_amdgcn_global_load_lds((glb_void_t *)src,
+                                         (lds_void_t *)(buf + (wave * 4 + j) * 1024), 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = (wave * 4 + j) * 16 + r_in;
+        const int c = swz(r, pos);
+        const int32_t k = min(k0 + r, K - 1);
+        const uint8_t *src = Wq + (size_t)k * pitch + kb + 16 * c;
+        __builtin_amdgcn_global_load_lds(
+            (glb_void_t *)src, (lds_void_t *)(buf + kBigT * kStageB + (wave * 4 + j) * 1024), 16,
+            0, 0);
+    }
+}
+
+template <int kMode>
+__global__ __launch_bounds__(256) void k_score_lp_big(const uint8_t *__restrict__ Xq,
+                                                      const float *__restrict__ sx, int32_t N,
+                                                      const uint8_t *__restrict__ Wq,
+                                                      const float *__restrict__ sw,
+                                                      const float *__restrict__ bias, int32_t K,
+                                                      int32_t pitch, float *__restrict__ S) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[kStages * kStageBytes];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    // Tile order as in k_score_lp: XCD-contiguous ranges, groups of row tiles.
+    const uint32_t nwg = gridDim.x, pid = blockIdx.x;
+    const uint32_t xcd = pid & 7u, per = nwg >> 3, rem = nwg & 7u;
+    const uint32_t L = xcd * per + min(xcd, rem) + (pid >> 3);
+    const uint32_t KT = (uint32_t)(K + kBigT - 1) / kBigT, NT = (uint32_t)(N + kBigT - 1) / kBigT;
+    const uint32_t g = L / (kGroupN * KT), i_g = L - g * (kGroupN * KT);
+    const uint32_t gn = min((uint32_t)kGroupN, NT - g * kGroupN);
+    const int32_t n0 = (int32_t)(g * kGroupN + i_g % gn) * kBigT;
+    const int32_t k0 = (int32_t)(i_g / gn) * kBigT;
+
+    f32x16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x16{};
+
+    const int nst = pitch / kStageB;
+    const int fr = lane & 31, fq = lane >> 5;
+#pragma unroll
+    for (int st = 0; st < kStages - 1; ++st)
+        if (st < nst) copy_stage(Xq, N, n0, Wq, K, k0, pitch, st * kStageB, lds + st * kStageBytes,
+                                 wave, lane);
+
+    for (int st = 0; st < nst; ++st) {
+        // Stage st landed (this wave's copies; the barrier covers the others'):
+        // at most kStages - 2 younger stages (8 copies each) may be pending.
+        const int younger = min(nst - 1 - st, kStages - 2);
+        if (younger >= 2) wait_vm<8 * 2>();
+        else if (younger == 1) wait_vm<8>();
+        else wait_vm<0>();
+        barrier_lds();
+        if (st + kStages - 1 < nst)
+            copy_stage(Xq, N, n0, Wq, K, k0, pitch, (st + kStages - 1) * kStageB,
+                       lds + ((st + kStages - 1) % kStages) * kStageBytes, wave, lane);
+        const uint8_t *bufA = lds + (st % kStages) * kStageBytes;
+        const uint8_t *bufB = bufA + kBigT * kStageB;
+        constexpr int kSubB = (kMode == LBPF_FP8_E4M3) ? 64 : 32;
+#pragma unroll
+        for (int sb = 0; sb < kStageB; sb += kSubB) {
+            u32x4 a[4][2], b[4][2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ra = wm * 128 + 32 * i + fr;
+                const int rb = wn * 128 + 32 * i + fr;
+                if constexpr (kMode == LBPF_FP8_E4M3) {
+                    // 32 bytes per lane: chunks 2 fq and 2 fq + 1 of the row.
+                    a[i][0] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, 2 * fq));
+                    a[i][1] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, 2 * fq + 1));
+                    b[i][0] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, 2 * fq));
+                    b[i][1] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, 2 * fq + 1));
+                } else {
+                    const int c = sb / 16 + fq;
+                    a[i][0] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, c));
+                    b[i][0] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, c));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_step<kMode>(a[i], b[j], acc[i][j], 0);
+        }
+    }
+
+    // 32 x 32 block layout: lane l, register r holds row 8 (r / 4) + 4 (l / 32)
+    // + r % 4 and column l % 32.
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int32_t k = k0 + wn * 128 + 32 * j + (lane & 31);
+        if (k >= K) continue;
+        const float swk = sw[k], bk = bias[k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int32_t n = n0 + wm * 128 + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (n < N) S[(size_t)n * K + k] = (sx[n] * swk) * acc[i][j][r] + bk;
+            }
+    }
+}
+
 }  // namespace
 
 int32_t lp_pitch(int32_t D, int32_t mode) {
@@ -284,6 +447,20 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
                            float *S, hipStream_t s) {
     if (N <= 0 || K <= 0) return hipSuccess;
     const int32_t pitch = lp_pitch(D, mode);
+    if (N >= 2 * kBigT && K >= kBigT) {
+        // Large products: 256 x 256 tiles fed through the LDS ring.
+        dim3 grid(((K + kBigT - 1) / kBigT) * ((N + kBigT - 1) / kBigT));
+        if (mode == LBPF_BF16)
+            hipLaunchKernelGGL(k_score_lp_big<LBPF_BF16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw,
+                               b, K, pitch, S);
+        else if (mode == LBPF_FP16)
+            hipLaunchKernelGGL(k_score_lp_big<LBPF_FP16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw,
+                               b, K, pitch, S);
+        else
+            hipLaunchKernelGGL(k_score_lp_big<LBPF_FP8_E4M3>, grid, dim3(256), 0, s, Xq, sx, N, Wq,
+                               sw, b, K, pitch, S);
+        return hipGetLastError();
+    }
     dim3 grid(((K + kTN - 1) / kTN) * ((N + kTM - 1) / kTM));
     if (mode == LBPF_BF16)
         hipLaunchKernelGGL(k_score_lp<LBPF_BF16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,

@@ -195,6 +195,34 @@ def test_scores_odd_dim(ref):
     c.close()
 
 
+def test_scores_other_dims_and_alignment(ref):
+    """The FP32 kernels by operand shape: D a multiple of 32 with aligned rows
+    (the LDS-ring kernel), D a multiple of 4 only (grey-only 4x4 grid, D =
+    944: vector loads), and rows that start off a 16-byte boundary."""
+    require_gpu()
+    c = lbpf.Context(grid=(4, 4), modality=lbpf.MOD_GREY)
+    assert c.dim % 32 != 0 and c.dim % 4 == 0
+    rng = np.random.default_rng(4)
+    for ctx_, N, K in ((c, 130, 70), (None, 200, 90)):
+        cc = ctx_ or lbpf.Context()
+        X = rng.random((N, cc.dim), dtype=np.float32)
+        W = rng.standard_normal((K, cc.dim), dtype=np.float32)
+        b = rng.standard_normal(K).astype(np.float32)
+        wts = cc.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda())
+        S, A = cc.score(torch.from_numpy(X).cuda(), wts)
+        torch.cuda.synchronize()
+        _check_scores(S.cpu().numpy(), A.cpu().numpy(), X, W, b, ref)
+        # The same rows one float into a larger buffer: not 16-byte aligned.
+        buf = torch.zeros(N * cc.dim + 1, dtype=torch.float32, device="cuda")
+        Xoff = buf[1:].view(N, cc.dim)
+        Xoff.copy_(torch.from_numpy(X))
+        S2, A2 = cc.score(Xoff, wts)
+        torch.cuda.synchronize()
+        _check_scores(S2.cpu().numpy(), A2.cpu().numpy(), X, W, b, ref)
+        wts.close()
+        cc.close()
+
+
 def test_argmax_only_matches_scores(ctx):
     rng = np.random.default_rng(9)
     X = torch.from_numpy(rng.random((300, ctx.dim), dtype=np.float32)).cuda()
