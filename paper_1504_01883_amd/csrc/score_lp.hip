@@ -269,11 +269,12 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
 // position chunk ^ ((row >> 1) & 3): the 16-byte fragment reads of 8
 // consecutive rows then hit 8 different bank groups.
 // The copy of stage s + kStages - 1 is issued right after the barrier that
-// opens stage s, so kStages - 1 stages are in flight while one is multiplied.
+// opens stage s, and the fragments of stage s + 1 are read into registers
+// while stage s is multiplied, so MFMAs after a barrier never wait for LDS.
 
 constexpr int kBigT = 256;      // tile rows and columns
 constexpr int kStageB = 64;     // bytes of the reduction per row and stage
-constexpr int kStages = 4;
+constexpr int kStages = 5;  // 5 x 32 KB: all of the 160 KB LDS
 constexpr int kStageBytes = 2 * kBigT * kStageB;  // A then B
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -357,15 +358,42 @@ __global__ __launch_bounds__(256) void k_score_lp_big(const uint8_t *__restrict_
 
     const int nst = pitch / kStageB;
     const int fr = lane & 31, fq = lane >> 5;
+    // Fragments of one stage: [block][h]. BF16/FP16: h = the 32-byte sub-step
+    // (this lane's 16 bytes of it); FP8: the two 16-byte halves of this lane's
+    // 32 bytes of the single 64-byte step.
+    auto read = [&](int st, u32x4 (&a)[4][2], u32x4 (&b)[4][2]) {
+        const uint8_t *bufA = lds + (st % kStages) * kStageBytes;
+        const uint8_t *bufB = bufA + kBigT * kStageB;
 #pragma unroll
-    for (int st = 0; st < kStages - 1; ++st)
-        if (st < nst) copy_stage(Xq, N, n0, Wq, K, k0, pitch, st * kStageB, lds + st * kStageBytes,
-                                 wave, lane);
-
-    for (int st = 0; st < nst; ++st) {
-        // Stage st landed (this wave's copies; the barrier covers the others'):
-        // at most kStages - 2 younger stages (8 copies each) may be pending.
-        const int younger = min(nst - 1 - st, kStages - 2);
+        for (int i = 0; i < 4; ++i) {
+            const int ra = wm * 128 + 32 * i + fr;
+            const int rb = wn * 128 + 32 * i + fr;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c = (kMode == LBPF_FP8_E4M3) ? 2 * fq + h : 2 * h + fq;
+                a[i][h] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, c));
+                b[i][h] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, c));
+            }
+        }
+    };
+    auto mma = [&](const u32x4 (&a)[4][2], const u32x4 (&b)[4][2]) {
+        constexpr int kSubs = (kMode == LBPF_FP8_E4M3) ? 1 : 2;
+#pragma unroll
+        for (int sub = 0; sub < kSubs; ++sub)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = mfma_step<kMode>(a[i], b[j], acc[i][j], sub);
+    };
+    // Iteration st: make stage st + 1 visible, start copying stage
+    // st + kStages - 1 into the buffer of stage st - 1 (read an iteration
+    // ago), read stage st + 1's fragments, multiply stage st's.
+    // Called for st + 1 < nst only (the last stage is multiplied on its own,
+    // so no path without a barrier joins the steady-state loop).
+    auto step = [&](int st, const u32x4 (&ca)[4][2], const u32x4 (&cb)[4][2], u32x4 (&na)[4][2],
+                    u32x4 (&nb)[4][2]) {
+        const int younger = min(nst - 2 - st, kStages - 3);
         if (younger >= 2) wait_vm<8 * 2>();
         else if (younger == 1) wait_vm<8>();
         else wait_vm<0>();
@@ -373,33 +401,33 @@ __global__ __launch_bounds__(256) void k_score_lp_big(const uint8_t *__restrict_
         if (st + kStages - 1 < nst)
             copy_stage(Xq, N, n0, Wq, K, k0, pitch, (st + kStages - 1) * kStageB,
                        lds + ((st + kStages - 1) % kStages) * kStageBytes, wave, lane);
-        const uint8_t *bufA = lds + (st % kStages) * kStageBytes;
-        const uint8_t *bufB = bufA + kBigT * kStageB;
-        constexpr int kSubB = (kMode == LBPF_FP8_E4M3) ? 64 : 32;
+        read(st + 1, na, nb);
+        mma(ca, cb);
+    };
 #pragma unroll
-        for (int sb = 0; sb < kStageB; sb += kSubB) {
-            u32x4 a[4][2], b[4][2];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int ra = wm * 128 + 32 * i + fr;
-                const int rb = wn * 128 + 32 * i + fr;
-                if constexpr (kMode == LBPF_FP8_E4M3) {
-                    // 32 bytes per lane: chunks 2 fq and 2 fq + 1 of the row.
-                    a[i][0] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, 2 * fq));
-                    a[i][1] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, 2 * fq + 1));
-                    b[i][0] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, 2 * fq));
-                    b[i][1] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, 2 * fq + 1));
-                } else {
-                    const int c = sb / 16 + fq;
-                    a[i][0] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, c));
-                    b[i][0] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, c));
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_step<kMode>(a[i], b[j], acc[i][j], 0);
-        }
+    for (int st = 0; st < kStages - 1; ++st)
+        if (st < nst) copy_stage(Xq, N, n0, Wq, K, k0, pitch, st * kStageB, lds + st * kStageBytes,
+                                 wave, lane);
+    {
+        const int younger = min(nst - 1, kStages - 2);
+        if (younger >= 3) wait_vm<8 * 3>();
+        else if (younger == 2) wait_vm<8 * 2>();
+        else if (younger == 1) wait_vm<8>();
+        else wait_vm<0>();
+    }
+    barrier_lds();
+    u32x4 a0[4][2], b0[4][2], a1[4][2], b1[4][2];
+    read(0, a0, b0);
+    int st = 0;
+    for (; st + 2 < nst; st += 2) {
+        step(st, a0, b0, a1, b1);
+        step(st + 1, a1, b1, a0, b0);
+    }
+    if (st + 1 < nst) {  // two stages left
+        step(st, a0, b0, a1, b1);
+        mma(a1, b1);
+    } else {
+        mma(a0, b0);
     }
 
     // 32 x 32 block layout: lane l, register r holds row 8 (r / 4) + 4 (l / 32)

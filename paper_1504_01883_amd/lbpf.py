@@ -284,6 +284,34 @@ class Graph:
             pass
 
 
+class ImageTable:
+    """A reusable lbpf_image array for a list of (grey, depth) device planes
+    (keeps the tensors alive)."""
+
+    def __init__(self, planes):
+        self.planes = list(planes)
+        self.arr = make_images(self.planes)
+        self.n = len(self.planes)
+        self.device = self.planes[0][1].device if self.planes else torch.device("cuda")
+
+
+class WarpBoxTable:
+    """A reusable lbpf_warp_box array: [(image, w, h, grey_frame, depth_frame)],
+    marshalled once for calls that repeat the same boxes."""
+
+    def __init__(self, boxes):
+        self.n = len(boxes)
+        rows = np.zeros((max(1, self.n), 15), np.int32)
+        for i, (im, w, h, gf, zf) in enumerate(boxes):
+            rows[i, 0:3] = (im, w, h)
+            rows[i, 3:9] = gf
+            rows[i, 9:15] = zf
+        self.arr = (WarpBox * max(1, self.n))()
+        ctypes.memmove(self.arr, rows.ctypes.data, rows.nbytes)
+        self.workspace_bytes = sum(int(load().lbpf_warp_crop_bytes(int(w), int(h)))
+                                   for (_, w, h, _, _) in boxes)
+
+
 class Context:
     """An lbpf_ctx on the current device."""
 
@@ -321,23 +349,23 @@ class Context:
         return hist, cnt
 
     def features_warped(self, planes, boxes, with_counts=False, out=None, workspace=None):
-        """Features of warped crops. boxes: [(image, w, h, grey_frame, depth_frame)]
-        with frames as 6-tuples (see box_frame / resize_frame). workspace: a
-        uint8 CUDA tensor (256-byte aligned); default: one sized for every crop."""
-        imgs = make_images(planes)
-        n = len(boxes)
-        arr = (WarpBox * max(1, n))()
-        for i, (im, w, h, gf, zf) in enumerate(boxes):
-            arr[i] = WarpBox(im, w, h, Frame(*[int(v) for v in gf]), Frame(*[int(v) for v in zf]))
-        dev = planes[0][1].device if planes else torch.device("cuda")
+        """Features of warped crops. planes: [(grey, depth)] device tensors or a
+        prepared ImageTable; boxes: [(image, w, h, grey_frame, depth_frame)] with
+        frames as 6-tuples (see box_frame / resize_frame), or a prepared
+        WarpBoxTable. workspace: a uint8 CUDA tensor (256-byte aligned);
+        default: one sized for every crop."""
+        imgs = planes if isinstance(planes, ImageTable) else ImageTable(planes)
+        tab = boxes if isinstance(boxes, WarpBoxTable) else WarpBoxTable(boxes)
+        n = tab.n
+        dev = imgs.device
         if workspace is None:
-            total = sum(int(load().lbpf_warp_crop_bytes(w, h)) for (_, w, h, _, _) in boxes)
-            workspace = torch.empty(max(total, 256), dtype=torch.uint8, device=dev)
+            workspace = torch.empty(max(tab.workspace_bytes, 256), dtype=torch.uint8, device=dev)
         hist = out if out is not None else torch.empty((n, self.dim), dtype=torch.float32,
                                                        device=dev)
         cnt = torch.empty((n, self.dim), dtype=torch.int32, device=dev) if with_counts else None
-        _check(load().lbpf_features_warped(self._h, imgs, len(planes), arr, n, _dptr(workspace),
-                                           workspace.numel(), _dptr(hist), _dptr(cnt), _stream()))
+        _check(load().lbpf_features_warped(self._h, imgs.arr, imgs.n, tab.arr, n,
+                                           _dptr(workspace), workspace.numel(), _dptr(hist),
+                                           _dptr(cnt), _stream()))
         return hist, cnt
 
     def train(self, X: torch.Tensor, labels: torch.Tensor, K: int, C=1.0, eps=1e-3,
