@@ -114,8 +114,15 @@ hipError_t launch_track(const int32_t *prev, const int32_t *ps, int32_t P, const
                         int32_t *owner, uint64_t *keys, hipStream_t s);
 
 // Scoring (score.hip).
+// FP32 scores. With D a multiple of 32 * splits and 16-byte aligned
+// operands the 128 x 128-tile kernel runs over `splits` ranges of D (partials
+// in part[splits][N][K], summed by a second kernel); otherwise the 64 x 64-tile
+// kernels run. splits: from score_f32_splits (1 when the tiles alone fill the
+// GPU); 0 selects the 64 x 64-tile kernels.
+int32_t score_f32_splits(int32_t N, int32_t K, int32_t D, int32_t num_cus, size_t part_elems);
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b,
-                            int32_t K, int32_t D, float *S, hipStream_t s);
+                            int32_t K, int32_t D, float *S, hipStream_t s, int32_t splits = 0,
+                            float *part = nullptr);
 hipError_t launch_argmax(const float *S, int32_t N, int32_t K, int32_t *argmax, hipStream_t s);
 
 }  // namespace lbpf

@@ -59,6 +59,7 @@ struct lbpf_ctx {
     uint8_t *d_xq = nullptr;            // reduced-precision scoring: quantised feature rows
     float *d_sx = nullptr;              //   and their scales, kLpChunkRows rows
     size_t xq_bytes = 0;
+    float *d_part = nullptr;            // FP32 scoring over split D: partial tiles
 };
 
 struct lbpf_batch {
@@ -91,6 +92,7 @@ struct lbpf_weights {
 namespace {
 
 constexpr size_t kScoreScratchElems = size_t(16) << 20;  // 64 MiB of FP32 scores
+constexpr size_t kPartElems = size_t(4) << 20;           // 16 MiB of split-D partial scores
 constexpr int32_t kLpChunkRows = 16384;                  // feature rows quantised per pass
 
 bool charge(lbpf_ctx *ctx, size_t bytes) {
@@ -203,7 +205,8 @@ lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_
 
     const size_t stage_bytes = sizeof(CropDesc) * LBPF_MAX_BOXES_PER_CALL;
     const size_t ws = 768 + kRing * stage_bytes + kScoreScratchElems * sizeof(float) +
-                      sizeof(int32_t) + sizeof(uint32_t) * (size_t)fp.dim;
+                      sizeof(int32_t) + sizeof(uint32_t) * (size_t)fp.dim +
+                      kPartElems * sizeof(float);
     if (!charge(ctx, ws)) return cleanup(fail(LBPF_E_BUDGET, "workspace exceeds the HBM budget"));
 
     // Tables: [0,256) code -> bin; [256,512) grey comparison byte -> bin;
@@ -232,6 +235,8 @@ lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_
         return cleanup(fail_hip(e, "hipMalloc"));
     if ((e = hipEventCreateWithFlags(&ctx->scratch_ev, hipEventDisableTiming)) != hipSuccess)
         return cleanup(fail_hip(e, "hipEventCreate"));
+    if ((e = hipMalloc((void **)&ctx->d_part, kPartElems * sizeof(float))) != hipSuccess)
+        return cleanup(fail_hip(e, "hipMalloc"));
     if ((e = hipMalloc((void **)&ctx->d_plain_median, sizeof(int32_t))) != hipSuccess)
         return cleanup(fail_hip(e, "hipMalloc"));
     if ((e = hipMalloc((void **)&ctx->d_plain_counts, sizeof(uint32_t) * fp.dim)) != hipSuccess)
@@ -256,6 +261,7 @@ void lbpf_destroy(lbpf_ctx *ctx) {
     if (ctx->d_xq) (void)hipFree(ctx->d_xq);
     if (ctx->d_sx) (void)hipFree(ctx->d_sx);
     if (ctx->d_plain_counts) (void)hipFree(ctx->d_plain_counts);
+    if (ctx->d_part) (void)hipFree(ctx->d_part);
     delete ctx;
 }
 
@@ -566,10 +572,16 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
     // otherwise as many as the context's score scratch holds.
     int32_t rows = scores_opt ? N : (int32_t)std::max<size_t>(1, ctx->scores_elems / K);
     if (w->prec != LBPF_FP32) rows = std::min(rows, kLpChunkRows);
-    // Calls that use the context's scratch (reduced precision, or argmax
-    // without caller scores) are ordered across streams by scratch_ev. Under
+    // FP32 products too small to fill the GPU with 128 x 128 tiles split D
+    // (partials in the context's scratch).
+    const int32_t splits =
+        w->prec == LBPF_FP32
+            ? score_f32_splits(std::min(rows, N), w->K, w->D, ctx->num_cus, kPartElems)
+            : 1;
+    // Calls that use the context's scratch (reduced precision, argmax without
+    // caller scores, split D) are ordered across streams by scratch_ev. Under
     // graph capture the graph's own order applies instead.
-    const bool uses_scratch = w->prec != LBPF_FP32 || !scores_opt;
+    const bool uses_scratch = w->prec != LBPF_FP32 || !scores_opt || splits > 1;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(s, &cap), "hipStreamIsCapturing");
     const bool order = uses_scratch && cap == hipStreamCaptureStatusNone;
@@ -578,7 +590,11 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
         const int32_t n = std::min(rows, N - n0);
         float *S = scores_opt ? scores_opt + (size_t)n0 * K : ctx->d_scores;
         if (w->prec == LBPF_FP32) {
-            HIP_TRY(launch_score_f32(hist + (size_t)n0 * D, n, w->W, w->b, w->K, w->D, S, s),
+            const int32_t sp = n == std::min(rows, N)
+                                   ? splits
+                                   : score_f32_splits(n, w->K, w->D, ctx->num_cus, kPartElems);
+            HIP_TRY(launch_score_f32(hist + (size_t)n0 * D, n, w->W, w->b, w->K, w->D, S, s, sp,
+                                     ctx->d_part),
                     "score launch");
         } else {
             HIP_TRY(launch_quant_rows(hist + (size_t)n0 * D, n, w->D, w->prec, ctx->d_xq,

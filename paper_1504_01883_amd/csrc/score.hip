@@ -2,13 +2,16 @@
 // argmax (Sec. 2.5: one hyperplane per enrolled person, the largest decision
 // value names the person).
 //
-// FP32 path: v_mfma_f32_16x16x4f32 (D[m][n] += sum_k A[m][k] B[k][n] over a
-// 16 x 16 x 4 block; lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-// and receives D[4 (l / 16) + t][l % 16], t = 0..3). Operands go straight
-// from global memory (L2) into VGPRs as float4: lane l loads row (l % 16) of
-// a block at columns d0 + 4 (l / 16) .. +3, and MFMA c (c = 0..3) consumes
-// component c, so four MFMAs cover 16 consecutive d exactly once for both
-// operands.
+// FP32 paths:
+//   * k_score_f32_split (D a multiple of 32 per split, 16-byte aligned rows):
+//     128 x 128 tiles streamed through LDS, described at the kernel;
+//   * k_score_f32 (any D): v_mfma_f32_16x16x4f32 (D[m][n] += sum_k A[m][k]
+//     B[k][n] over a 16 x 16 x 4 block; lane l supplies A[l % 16][l / 16] and
+//     B[l / 16][l % 16] and receives D[4 (l / 16) + t][l % 16], t = 0..3).
+//     Operands go straight from global memory (L2) into VGPRs as float4: lane
+//     l loads row (l % 16) of a block at columns d0 + 4 (l / 16) .. +3, and
+//     MFMA c (c = 0..3) consumes component c, so four MFMAs cover 16
+//     consecutive d exactly once for both operands.
 #include "lbpf_internal.h"
 
 namespace lbpf {
@@ -162,31 +165,6 @@ __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ S, int
     if (lane == 0) out[n] = arg;
 }
 
-// --- FP32, LDS ring --------------------------------------------------------------
-//
-// For D a multiple of 32 and 16-byte aligned operands. A workgroup of 8 waves
-// owns a 64 x 64 tile of S; waves 0-3 take the first half of the feature
-// dimension and waves 4-7 the second (two waves per SIMD), and wave t of a
-// half computes the 32 x 32 block (rows 32 (t & 1), columns 32 (t >> 1)) with
-// v_mfma_f32_32x32x2f32 (lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32];
-// D: register r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32).
-// Each half streams 64-byte slices of its 64 X rows and 64 W rows through a
-// ring of kRing LDS stages with global_load_lds_dwordx4 (wave t copies 32 rows
-// of X (t < 2) or W (t >= 2), two 1 KB instructions per stage), issued
-// kRing - 1 stages ahead; each stage's fragments are read into registers one
-// stage before they are multiplied, so the MFMAs after a barrier never wait
-// for LDS. Chunk c (16 bytes) of row r sits at position
-// c ^ ((r >> 1) & 3) of the row so that fragment reads of 8 consecutive rows
-// hit 8 bank groups. A lane reads a 16-byte chunk (4 consecutive d) of its
-// row and feeds its components to 4 MFMAs: step s pairs d = 4 q + s of lanes
-// with l / 32 = q, so every d of the slice is used once by both operands.
-// At the end the second half's blocks go through LDS and are added to the
-// first half's in a fixed order, then the bias.
-
-constexpr int kRing = 8;
-constexpr int kSliceB = 64;                        // bytes per row and stage
-constexpr int kHalfStage = 2 * 64 * kSliceB;       // X rows then W rows: 8 KB
-
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) const void glb_void_t;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -198,16 +176,18 @@ __device__ __forceinline__ void wait_vm() {
     __builtin_amdgcn_s_waitcnt((kVm & 15) | (7 << 4) | (15 << 8) | ((kVm >> 4) << 14));
 }
 
-// Wait until at most 2 * `younger` of this wave's copies are in flight.
+// Wait until at most kPer * younger of this wave's copies are in flight.
+template <int kPer>
 __device__ __forceinline__ void wait_stage(int younger) {
     switch (younger) {
         case 0: wait_vm<0>(); break;
-        case 1: wait_vm<2>(); break;
-        case 2: wait_vm<4>(); break;
-        case 3: wait_vm<6>(); break;
-        case 4: wait_vm<8>(); break;
-        case 5: wait_vm<10>(); break;
-        default: wait_vm<12>(); break;
+        case 1: wait_vm<kPer>(); break;
+        case 2: wait_vm<2 * kPer>(); break;
+        case 3: wait_vm<3 * kPer>(); break;
+        case 4: wait_vm<4 * kPer>(); break;
+        case 5: wait_vm<5 * kPer>(); break;
+        case 6: wait_vm<6 * kPer>(); break;
+        default: wait_vm<7 * kPer>(); break;
     }
 }
 
@@ -221,95 +201,105 @@ __device__ __forceinline__ void barrier_lds() {
     asm volatile("" ::: "memory");
 }
 
-__device__ __forceinline__ int fswz(int row, int chunk) { return chunk ^ ((row >> 1) & 3); }
+// --- FP32, 128 x 128 tiles, split feature dimension --------------------------------
+//
+// A workgroup of 4 waves owns a 128 x 128 tile of S over one of `splits`
+// equal ranges of the feature dimension; wave w computes the 64 x 64 quarter
+// (rows 64 (w & 1), columns 64 (w >> 1)) as 2 x 2 blocks of 32 x 32 (four
+// independent accumulator chains). 128-byte slices of the 128 X rows and 128
+// W rows stream through a ring of kRingN 32 KB stages (global_load_lds; each
+// wave copies 32 rows of each; chunk c of row r at position c ^ (r % 8)), and
+// a stage's fragments are read one stage ahead. The barrier per stage orders
+// LDS only (barrier_lds), so the copies of later stages stay in flight.
+// With splits > 1 every workgroup stores its partial tile and k_split_reduce,
+// queued after it on the same stream, adds the partials in split order and
+// the bias. (Reducing inside the kernel would need device-scope fences, which
+// on this GPU write back and invalidate the XCD's L2 under the tiles still
+// streaming through it.)
 
-__global__ __launch_bounds__(512) void k_score_f32_ring(const float *__restrict__ X, int32_t N,
-                                                        const float *__restrict__ W,
-                                                        const float *__restrict__ bias,
-                                                        int32_t K, int32_t D,
-                                                        float *__restrict__ S) {
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * kRing * kHalfStage];  // 128 KB
+template <int kRingN>
+__global__ __launch_bounds__(256) void k_score_f32_split(
+    const float *__restrict__ X, int32_t N, const float *__restrict__ W,
+    const float *__restrict__ bias, int32_t K, int32_t D, float *__restrict__ S, int32_t splits,
+    float *__restrict__ part) {
+    constexpr int kSlice = 128, kT = 128;
+    constexpr int kStage = 2 * kT * kSlice;  // X rows then W rows: 32 KB
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[kRingN * kStage];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int half = wave >> 2, t = wave & 3;
-    const int32_t n0 = blockIdx.x * kTile, k0 = blockIdx.y * kTile;
-    const int32_t dh = D / 2;
-    const int nst = dh / (kSliceB / 4);
-    uint8_t *ring = lds + half * kRing * kHalfStage;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int32_t n0 = blockIdx.x * kT, k0 = blockIdx.y * kT, sp = blockIdx.z;
+    const int32_t dsp = D / splits, d0 = sp * dsp;
+    const int nst = dsp / (kSlice / 4);
+    auto swz = [](int row, int chunk) { return chunk ^ (row & 7); };
 
-    // Copy role: 32 rows of X (t < 2) or W (t >= 2); lane i -> row i / 4 of
-    // each 16-row kilobyte, position i % 4.
-    const bool isx = t < 2;
-    const float *mat = isx ? X : W;
-    const int32_t lim = isx ? N : K, base = isx ? n0 : k0;
-    const int rr = lane >> 2, pos = lane & 3;
-    const float *src[2];
-    int dst_off[2];
+    // Copy role: rows 32 w .. +31 of X and of W, 8 rows per 1 KB instruction;
+    // lane i -> row i / 8 of its kilobyte, position i % 8.
+    const int rr = lane >> 3, pos = lane & 7;
+    const float *src[8];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int row = (t & 1) * 32 + j * 16 + rr;  // 0..63 within X or W
-        const int32_t g = min(base + row, lim - 1);
-        src[j] = mat + (size_t)g * D + (size_t)half * dh + 4 * fswz(row, pos);
-        dst_off[j] = (isx ? 0 : 64 * kSliceB) + ((t & 1) * 32 + j * 16) * kSliceB;
+    for (int j = 0; j < 8; ++j) {
+        const bool isx = j < 4;
+        const int row = wave * 32 + (j & 3) * 8 + rr;
+        const int32_t g = isx ? min(n0 + row, N - 1) : min(k0 + row, K - 1);
+        src[j] = (isx ? X : W) + (size_t)g * D + d0 + 4 * swz(row, pos);
     }
     auto copy = [&](int st) {
-        uint8_t *stage = ring + (st % kRing) * kHalfStage;
+        uint8_t *stage = lds + (st % kRingN) * kStage;
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            __builtin_amdgcn_global_load_lds((glb_void_t *)(src[j] + st * (kSliceB / 4)),
-                                             (lds_void_t *)(stage + dst_off[j]), 16, 0, 0);
+        for (int j = 0; j < 8; ++j)
+            __builtin_amdgcn_global_load_lds(
+                (glb_void_t *)(src[j] + st * (kSlice / 4)),
+                (lds_void_t *)(stage + (j < 4 ? 0 : kT * kSlice) + (wave * 32 + (j & 3) * 8) * kSlice),
+                16, 0, 0);
     };
 
     const int fr = lane & 31, fq = lane >> 5;
-    const int ra = (t & 1) * 32 + fr, rb = (t >> 1) * 32 + fr;
-    // Byte offsets of this lane's fragments within a stage, chunk pair c.
-    int oa[2], ob[2];
+    int oa[2][4], ob[2][4];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        oa[c] = ra * kSliceB + 16 * fswz(ra, 2 * c + fq);
-        ob[c] = 64 * kSliceB + rb * kSliceB + 16 * fswz(rb, 2 * c + fq);
-    }
-    auto read = [&](int st, floatx4 (&a)[2], floatx4 (&b)[2]) {
-        const uint8_t *stage = ring + (st % kRing) * kHalfStage;
+    for (int i = 0; i < 2; ++i) {
+        const int ra = wm * 64 + 32 * i + fr, rb = wn * 64 + 32 * i + fr;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            a[c] = *reinterpret_cast<const floatx4 *>(stage + oa[c]);
-            b[c] = *reinterpret_cast<const floatx4 *>(stage + ob[c]);
+        for (int p = 0; p < 4; ++p) {
+            oa[i][p] = ra * kSlice + 16 * swz(ra, 2 * p + fq);
+            ob[i][p] = kT * kSlice + rb * kSlice + 16 * swz(rb, 2 * p + fq);
         }
+    }
+    typedef floatx4 Frag[2][4];
+    auto read = [&](int st, Frag &a, Frag &b) {
+        const uint8_t *stage = lds + (st % kRingN) * kStage;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                a[i][p] = *reinterpret_cast<const floatx4 *>(stage + oa[i][p]);
+                b[i][p] = *reinterpret_cast<const floatx4 *>(stage + ob[i][p]);
+            }
     };
-    // Four independent accumulator chains (chunk pair c, parity of the
-    // component), interleaved so that an accumulator recurs only every fourth
-    // MFMA of the wave; summed at the end.
-    floatx16 acc4[4] = {{}, {}, {}, {}};
-    auto mma = [&](const floatx4 (&a)[2], const floatx4 (&b)[2]) {
-        acc4[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0].x, b[0].x, acc4[0], 0, 0, 0);
-        acc4[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1].x, b[1].x, acc4[1], 0, 0, 0);
-        acc4[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0].y, b[0].y, acc4[2], 0, 0, 0);
-        acc4[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1].y, b[1].y, acc4[3], 0, 0, 0);
-        acc4[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0].z, b[0].z, acc4[0], 0, 0, 0);
-        acc4[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1].z, b[1].z, acc4[1], 0, 0, 0);
-        acc4[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0].w, b[0].w, acc4[2], 0, 0, 0);
-        acc4[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1].w, b[1].w, acc4[3], 0, 0, 0);
+    floatx16 acc[2][2] = {{{}, {}}, {{}, {}}};
+    auto mma = [&](const Frag &a, const Frag &b) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][p][c], b[j][p][c],
+                                                                          acc[i][j], 0, 0, 0);
     };
-    // Iteration st: make stage st + 1 visible, start the copy of stage
-    // st + kRing - 1 (into the buffer stage st - 1 used, whose fragments were
-    // read an iteration earlier), read stage st + 1's fragments, multiply stage
-    // st's (read during the previous iteration).
-    // Called for st + 1 < nst only: the last stage is multiplied on its own,
-    // so that no path without a barrier joins the steady-state loop (that
-    // join would make the compiler wait for the fresh fragment reads).
-    auto step = [&](int st, const floatx4 (&ca)[2], const floatx4 (&cb)[2], floatx4 (&na)[2],
-                    floatx4 (&nb)[2]) {
-        wait_stage(min(nst - 2 - st, kRing - 3));
+    auto step = [&](int st, const Frag &ca, const Frag &cb, Frag &na, Frag &nb) {
+        wait_stage<8>(min(nst - 2 - st, kRingN - 3));
         barrier_lds();
-        if (st + kRing - 1 < nst) copy(st + kRing - 1);
+        if (st + kRingN - 1 < nst) copy(st + kRingN - 1);
         read(st + 1, na, nb);
         mma(ca, cb);
     };
 #pragma unroll
-    for (int st = 0; st < kRing - 1; ++st)
+    for (int st = 0; st < kRingN - 1; ++st)
         if (st < nst) copy(st);
-    floatx4 a0[2], b0[2], a1[2], b1[2];
-    wait_stage(min(nst - 1, kRing - 2));
+    Frag a0, b0, a1, b1;
+    wait_stage<8>(min(nst - 1, kRingN - 2));
     barrier_lds();
     read(0, a0, b0);
     int st = 0;
@@ -317,44 +307,89 @@ __global__ __launch_bounds__(512) void k_score_f32_ring(const float *__restrict_
         step(st, a0, b0, a1, b1);
         step(st + 1, a1, b1, a0, b0);
     }
-    if (st + 1 < nst) {  // two stages left
+    if (st + 1 < nst) {
         step(st, a0, b0, a1, b1);
         mma(a1, b1);
     } else {
         mma(a0, b0);
     }
 
-    const floatx16 acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-    // Second half -> LDS -> added to the first half's block.
-    __syncthreads();
-    floatx16 *part = reinterpret_cast<floatx16 *>(lds);
-    if (half == 1) part[t * 64 + lane] = acc;
-    __syncthreads();
-    if (half == 0) {
-        const floatx16 o = part[t * 64 + lane];
-        const int32_t k = k0 + (t >> 1) * 32 + (lane & 31);
-        if (k < K) {
-            const float bk = bias[k];
+    // 32 x 32 block layout: register r of lane l is row 8 (r / 4) + 4 (l / 32)
+    // + r % 4, column l % 32.
+    auto for_each = [&](auto &&f) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int32_t n = n0 + (t & 1) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (n < N) S[(size_t)n * K + k] = (acc[r] + o[r]) + bk;
-            }
+        for (int j = 0; j < 2; ++j) {
+            const int32_t k = k0 + wn * 64 + 32 * j + (lane & 31);
+            if (k >= K) continue;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t n = n0 + wm * 64 + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    if (n < N) f(i, j, r, n, k);
+                }
         }
+    };
+    if (splits == 1) {
+        for_each([&](int i, int j, int r, int32_t n, int32_t k) {
+            S[(size_t)n * K + k] = acc[i][j][r] + bias[k];
+        });
+        return;
+    }
+    const size_t plane = (size_t)N * K;
+    for_each([&](int i, int j, int r, int32_t n, int32_t k) {
+        part[(size_t)sp * plane + (size_t)n * K + k] = acc[i][j][r];
+    });
+}
+
+// S = (((part_0 + part_1) + part_2) + ...) + b, four elements per thread.
+__global__ __launch_bounds__(256) void k_split_reduce(const float *__restrict__ part,
+                                                      int32_t splits, int32_t N, int32_t K,
+                                                      const float *__restrict__ bias,
+                                                      float *__restrict__ S) {
+    const size_t plane = (size_t)N * K;
+    const size_t e0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const size_t e = e0 + u;
+        if (e >= plane) return;
+        float sum = part[e];
+        for (int q = 1; q < splits; ++q) sum += part[(size_t)q * plane + e];
+        S[e] = sum + bias[e % (size_t)K];
     }
 }
 
 }  // namespace
 
+int32_t score_f32_splits(int32_t N, int32_t K, int32_t D, int32_t num_cus, size_t part_elems) {
+    const int64_t tiles = (int64_t)((N + 127) / 128) * ((K + 127) / 128);
+    int32_t best = 1;
+    for (int32_t sp = 2; sp <= 4; sp *= 2) {
+        if (tiles * best >= num_cus) break;  // enough workgroups already
+        if (D % (32 * sp) != 0) break;
+        if ((size_t)sp * (size_t)N * (size_t)K > part_elems) break;
+        best = sp;
+    }
+    return best;
+}
+
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b, int32_t K,
-                            int32_t D, float *S, hipStream_t s) {
+                            int32_t D, float *S, hipStream_t s, int32_t splits, float *part) {
     if (N <= 0 || K <= 0) return hipSuccess;
-    dim3 grid((N + kTile - 1) / kTile, (K + kTile - 1) / kTile);
-    const bool vec = (D % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
-    if (vec && D % 32 == 0) {
-        hipLaunchKernelGGL(k_score_f32_ring, grid, dim3(512), 0, s, X, N, W, b, K, D, S);
+    const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
+    if (aligned && splits >= 1 && D % (32 * splits) == 0 && (splits == 1 || part)) {
+        dim3 g((N + 127) / 128, (K + 127) / 128, splits);
+        hipLaunchKernelGGL(k_score_f32_split<4>, g, dim3(256), 0, s, X, N, W, b, K, D, S, splits,
+                           part);
+        if (splits > 1) {
+            const size_t elems = (size_t)N * K;
+            hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((elems + 1023) / 1024)), dim3(256),
+                               0, s, part, splits, N, K, b, S);
+        }
         return hipGetLastError();
     }
+    dim3 grid((N + kTile - 1) / kTile, (K + kTile - 1) / kTile);
+    const bool vec = (D % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
     if (vec)
         hipLaunchKernelGGL(k_score_f32<true>, grid, dim3(512), 0, s, X, N, W, b, K, D, S);
     else

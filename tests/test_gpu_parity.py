@@ -196,14 +196,17 @@ def test_scores_odd_dim(ref):
 
 
 def test_scores_other_dims_and_alignment(ref):
-    """The FP32 kernels by operand shape: D a multiple of 32 with aligned rows
-    (the LDS-ring kernel), D a multiple of 4 only (grey-only 4x4 grid, D =
-    944: vector loads), and rows that start off a 16-byte boundary."""
+    """The FP32 kernels by operand shape: D a multiple of 32 (7552 and the 4x4
+    grid's 1888: the LDS-streamed 128 x 128 tiles, split or not), of 4 only
+    (grey-only 4x4 grid, 944: vector loads), and rows that start off a
+    16-byte boundary."""
     require_gpu()
     c = lbpf.Context(grid=(4, 4), modality=lbpf.MOD_GREY)
+    c2 = lbpf.Context(grid=(4, 4))
     assert c.dim % 32 != 0 and c.dim % 4 == 0
+    assert c2.dim % 32 == 0
     rng = np.random.default_rng(4)
-    for ctx_, N, K in ((c, 130, 70), (None, 200, 90)):
+    for ctx_, N, K in ((c, 130, 70), (c2, 150, 80), (None, 200, 90)):
         cc = ctx_ or lbpf.Context()
         X = rng.random((N, cc.dim), dtype=np.float32)
         W = rng.standard_normal((K, cc.dim), dtype=np.float32)
