@@ -116,13 +116,14 @@ hipError_t launch_track(const int32_t *prev, const int32_t *ps, int32_t P, const
 // Scoring (score.hip).
 // FP32 scores. With D a multiple of 32 * splits and 16-byte aligned
 // operands the 128 x 128-tile kernel runs over `splits` ranges of D (partials
-// in part[splits][N][K], summed by a second kernel); otherwise the 64 x 64-tile
+// in part[splits][N][K], summed with the argmax by a second kernel); otherwise the 64 x 64-tile
 // kernels run. splits: from score_f32_splits (1 when the tiles alone fill the
 // GPU); 0 selects the 64 x 64-tile kernels.
 int32_t score_f32_splits(int32_t N, int32_t K, int32_t D, int32_t num_cus, size_t part_elems);
+// S is always written; argmax (may be null) gets each row's best identity.
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b,
-                            int32_t K, int32_t D, float *S, hipStream_t s, int32_t splits = 0,
-                            float *part = nullptr);
+                            int32_t K, int32_t D, float *S, int32_t *argmax, hipStream_t s,
+                            int32_t splits = 0, float *part = nullptr);
 hipError_t launch_argmax(const float *S, int32_t N, int32_t K, int32_t *argmax, hipStream_t s);
 
 }  // namespace lbpf

@@ -593,8 +593,8 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
             const int32_t sp = n == std::min(rows, N)
                                    ? splits
                                    : score_f32_splits(n, w->K, w->D, ctx->num_cus, kPartElems);
-            HIP_TRY(launch_score_f32(hist + (size_t)n0 * D, n, w->W, w->b, w->K, w->D, S, s, sp,
-                                     ctx->d_part),
+            HIP_TRY(launch_score_f32(hist + (size_t)n0 * D, n, w->W, w->b, w->K, w->D, S,
+                                     argmax_opt ? argmax_opt + n0 : nullptr, s, sp, ctx->d_part),
                     "score launch");
         } else {
             HIP_TRY(launch_quant_rows(hist + (size_t)n0 * D, n, w->D, w->prec, ctx->d_xq,
@@ -603,8 +603,9 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
             HIP_TRY(launch_score_lp(ctx->d_xq, ctx->d_sx, n, w->Wq, w->sw, w->b, w->K, w->D,
                                     w->prec, S, s),
                     "score launch");
+            if (argmax_opt)
+                HIP_TRY(launch_argmax(S, n, w->K, argmax_opt + n0, s), "argmax launch");
         }
-        if (argmax_opt) HIP_TRY(launch_argmax(S, n, w->K, argmax_opt + n0, s), "argmax launch");
     }
     if (order) HIP_TRY(hipEventRecord(ctx->scratch_ev, s), "hipEventRecord");
     return LBPF_OK;

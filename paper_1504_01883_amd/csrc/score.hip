@@ -211,9 +211,9 @@ __device__ __forceinline__ void barrier_lds() {
 // wave copies 32 rows of each; chunk c of row r at position c ^ (r % 8)), and
 // a stage's fragments are read one stage ahead. The barrier per stage orders
 // LDS only (barrier_lds), so the copies of later stages stay in flight.
-// With splits > 1 every workgroup stores its partial tile and k_split_reduce,
+// With splits > 1 every workgroup stores its partial tile and k_reduce_argmax,
 // queued after it on the same stream, adds the partials in split order and
-// the bias. (Reducing inside the kernel would need device-scope fences, which
+// the bias (and takes the argmax in the same pass). (Reducing inside the kernel would need device-scope fences, which
 // on this GPU write back and invalidate the XCD's L2 under the tiles still
 // streaming through it.)
 
@@ -342,21 +342,41 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
     });
 }
 
-// S = (((part_0 + part_1) + part_2) + ...) + b, four elements per thread.
-__global__ __launch_bounds__(256) void k_split_reduce(const float *__restrict__ part,
-                                                      int32_t splits, int32_t N, int32_t K,
-                                                      const float *__restrict__ bias,
-                                                      float *__restrict__ S) {
-    const size_t plane = (size_t)N * K;
-    const size_t e0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const size_t e = e0 + u;
-        if (e >= plane) return;
-        float sum = part[e];
-        for (int q = 1; q < splits; ++q) sum += part[(size_t)q * plane + e];
-        S[e] = sum + bias[e % (size_t)K];
+// Split-D epilogue, one wave per row: S = (((part_0 + part_1) + ...) + b in
+// split order, and (optionally) the row's argmax, ties to the lowest index as
+// in k_argmax.
+__global__ __launch_bounds__(256) void k_reduce_argmax(const float *__restrict__ part,
+                                                       int32_t splits, int32_t N, int32_t K,
+                                                       const float *__restrict__ bias,
+                                                       float *__restrict__ S,
+                                                       int32_t *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int32_t n = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (n >= N) return;
+    const size_t plane = (size_t)N * K, row = (size_t)n * K;
+    float best = -INFINITY;
+    int32_t arg = K;
+    for (int32_t k = lane; k < K; k += 64) {
+        float v = part[row + k];
+        for (int q = 1; q < splits; ++q) v += part[(size_t)q * plane + row + k];
+        v += bias[k];
+        S[row + k] = v;
+        if (v > best || arg == K) {
+            best = v;
+            arg = k;
+        }
     }
+    if (!out) return;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float ob = __shfl_xor(best, off, 64);
+        const int32_t oa = __shfl_xor(arg, off, 64);
+        if (ob > best || (ob == best && oa < arg)) {
+            best = ob;
+            arg = oa;
+        }
+    }
+    if (lane == 0) out[n] = arg;
 }
 
 }  // namespace
@@ -374,7 +394,8 @@ int32_t score_f32_splits(int32_t N, int32_t K, int32_t D, int32_t num_cus, size_
 }
 
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b, int32_t K,
-                            int32_t D, float *S, hipStream_t s, int32_t splits, float *part) {
+                            int32_t D, float *S, int32_t *argmax, hipStream_t s, int32_t splits,
+                            float *part) {
     if (N <= 0 || K <= 0) return hipSuccess;
     const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
     if (aligned && splits >= 1 && D % (32 * splits) == 0 && (splits == 1 || part)) {
@@ -382,11 +403,13 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
         hipLaunchKernelGGL(k_score_f32_split<4>, g, dim3(256), 0, s, X, N, W, b, K, D, S, splits,
                            part);
         if (splits > 1) {
-            const size_t elems = (size_t)N * K;
-            hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((elems + 1023) / 1024)), dim3(256),
-                               0, s, part, splits, N, K, b, S);
+            hipLaunchKernelGGL(k_reduce_argmax, dim3((N + 3) / 4), dim3(256), 0, s, part, splits,
+                               N, K, b, S, argmax);
+            return hipGetLastError();
         }
-        return hipGetLastError();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !argmax) return e;
+        return launch_argmax(S, N, K, argmax, s);
     }
     dim3 grid((N + kTile - 1) / kTile, (K + kTile - 1) / kTile);
     const bool vec = (D % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
@@ -394,7 +417,9 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
         hipLaunchKernelGGL(k_score_f32<true>, grid, dim3(512), 0, s, X, N, W, b, K, D, S);
     else
         hipLaunchKernelGGL(k_score_f32<false>, grid, dim3(512), 0, s, X, N, W, b, K, D, S);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !argmax) return e;
+    return launch_argmax(S, N, K, argmax, s);
 }
 
 hipError_t launch_argmax(const float *S, int32_t N, int32_t K, int32_t *argmax, hipStream_t s) {
