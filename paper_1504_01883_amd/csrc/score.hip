@@ -288,18 +288,21 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][p][c], b[j][p][c],
                                                                           acc[i][j], 0, 0, 0);
     };
+    // Stage st's buffer is free once its fragments are in registers (read
+    // during the previous step, before this step's barrier), so the copy of
+    // stage st + kRingN goes there: kRingN - 1 stages stay in flight.
     auto step = [&](int st, const Frag &ca, const Frag &cb, Frag &na, Frag &nb) {
-        wait_stage<8>(min(nst - 2 - st, kRingN - 3));
+        wait_stage<8>(min(nst - 2 - st, kRingN - 2));
         barrier_lds();
-        if (st + kRingN - 1 < nst) copy(st + kRingN - 1);
+        if (st + kRingN < nst) copy(st + kRingN);
         read(st + 1, na, nb);
         mma(ca, cb);
     };
 #pragma unroll
-    for (int st = 0; st < kRingN - 1; ++st)
+    for (int st = 0; st < kRingN; ++st)
         if (st < nst) copy(st);
     Frag a0, b0, a1, b1;
-    wait_stage<8>(min(nst - 1, kRingN - 2));
+    wait_stage<8>(min(nst - 1, kRingN - 1));
     barrier_lds();
     read(0, a0, b0);
     int st = 0;

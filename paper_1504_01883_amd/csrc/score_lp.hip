@@ -268,9 +268,9 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
 // row i / 4, position i % 4. Within a row the four chunks are stored at
 // position chunk ^ ((row >> 1) & 3): the 16-byte fragment reads of 8
 // consecutive rows then hit 8 different bank groups.
-// The copy of stage s + kStages - 1 is issued right after the barrier that
-// opens stage s, and the fragments of stage s + 1 are read into registers
-// while stage s is multiplied, so MFMAs after a barrier never wait for LDS.
+// The fragments of stage s + 1 are read into registers while stage s is
+// multiplied, so MFMAs after a barrier never wait for LDS, and the copy of
+// stage s + kStages, issued right after that barrier, reuses stage s's buffer.
 
 constexpr int kBigT = 256;      // tile rows and columns
 constexpr int kStageB = 64;     // bytes of the reduction per row and stage
@@ -390,31 +390,32 @@ __global__ __launch_bounds__(256) void k_score_lp_big(const uint8_t *__restrict_
     // st + kStages - 1 into the buffer of stage st - 1 (read an iteration
     // ago), read stage st + 1's fragments, multiply stage st's.
     // Called for st + 1 < nst only (the last stage is multiplied on its own,
-    // so no path without a barrier joins the steady-state loop).
-    auto step = [&](int st, const u32x4 (&ca)[4][2], const u32x4 (&cb)[4][2], u32x4 (&na)[4][2],
-                    u32x4 (&nb)[4][2]) {
-        const int younger = min(nst - 2 - st, kStages - 3);
-        if (younger >= 2) wait_vm<8 * 2>();
+    // so no path without a barrier joins the steady-state loop). Stage st's
+    // buffer is free once its fragments are in registers (read during the
+    // previous step, before this step's barrier), so the copy of stage
+    // st + kStages goes there: kStages - 1 stages stay in flight.
+    auto wait_younger = [](int younger) {
+        if (younger >= 4) wait_vm<8 * 4>();
+        else if (younger == 3) wait_vm<8 * 3>();
+        else if (younger == 2) wait_vm<8 * 2>();
         else if (younger == 1) wait_vm<8>();
         else wait_vm<0>();
+    };
+    auto step = [&](int st, const u32x4 (&ca)[4][2], const u32x4 (&cb)[4][2], u32x4 (&na)[4][2],
+                    u32x4 (&nb)[4][2]) {
+        wait_younger(min(nst - 2 - st, kStages - 2));
         barrier_lds();
-        if (st + kStages - 1 < nst)
-            copy_stage(Xq, N, n0, Wq, K, k0, pitch, (st + kStages - 1) * kStageB,
-                       lds + ((st + kStages - 1) % kStages) * kStageBytes, wave, lane);
+        if (st + kStages < nst)
+            copy_stage(Xq, N, n0, Wq, K, k0, pitch, (st + kStages) * kStageB,
+                       lds + (st % kStages) * kStageBytes, wave, lane);
         read(st + 1, na, nb);
         mma(ca, cb);
     };
 #pragma unroll
-    for (int st = 0; st < kStages - 1; ++st)
+    for (int st = 0; st < kStages; ++st)
         if (st < nst) copy_stage(Xq, N, n0, Wq, K, k0, pitch, st * kStageB, lds + st * kStageBytes,
                                  wave, lane);
-    {
-        const int younger = min(nst - 1, kStages - 2);
-        if (younger >= 3) wait_vm<8 * 3>();
-        else if (younger == 2) wait_vm<8 * 2>();
-        else if (younger == 1) wait_vm<8>();
-        else wait_vm<0>();
-    }
+    wait_younger(min(nst - 1, kStages - 1));
     barrier_lds();
     u32x4 a0[4][2], b0[4][2], a1[4][2], b1[4][2];
     read(0, a0, b0);
