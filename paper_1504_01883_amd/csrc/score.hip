@@ -217,66 +217,84 @@ __device__ __forceinline__ void barrier_lds() {
 // on this GPU write back and invalidate the XCD's L2 under the tiles still
 // streaming through it.)
 
-template <int kRingN>
+template <int kRingN, int kTK>
 __global__ __launch_bounds__(256) void k_score_f32_split(
     const float *__restrict__ X, int32_t N, const float *__restrict__ W,
     const float *__restrict__ bias, int32_t K, int32_t D, float *__restrict__ S, int32_t splits,
     float *__restrict__ part) {
-    constexpr int kSlice = 128, kT = 128;
-    constexpr int kStage = 2 * kT * kSlice;  // X rows then W rows: 32 KB
+    // Tile: 128 feature rows x kTK identities (kTK = 128 or 64); wave w owns
+    // rows 64 (w & 1) .. +64 and identities (kTK / 2) (w >> 1) .. + kTK / 2 as
+    // 2 x kJB blocks of 32 x 32.
+    constexpr int kSlice = 128, kTM = 128;
+    constexpr int kJB = kTK / 64;                          // 32-wide blocks per wave
+    constexpr int kWRows = kTK / 4;                        // W rows each wave copies
+    constexpr int kCopies = 4 + kWRows / 8;                // 1 KB copies per wave and stage
+    constexpr int kStage = (kTM + kTK) * kSlice;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[kRingN * kStage];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int32_t n0 = blockIdx.x * kT, k0 = blockIdx.y * kT, sp = blockIdx.z;
+    const int32_t n0 = blockIdx.x * kTM, k0 = blockIdx.y * kTK, sp = blockIdx.z;
     const int32_t dsp = D / splits, d0 = sp * dsp;
     const int nst = dsp / (kSlice / 4);
     auto swz = [](int row, int chunk) { return chunk ^ (row & 7); };
 
-    // Copy role: rows 32 w .. +31 of X and of W, 8 rows per 1 KB instruction;
-    // lane i -> row i / 8 of its kilobyte, position i % 8.
+    // Copy role: X rows 32 w .. +31 (4 copies of 8 rows) and W rows
+    // kWRows w .. + kWRows; lane i -> row i / 8 of its kilobyte, position i % 8.
     const int rr = lane >> 3, pos = lane & 7;
-    const float *src[8];
+    const float *src[kCopies];
+    int dst[kCopies];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < kCopies; ++j) {
         const bool isx = j < 4;
-        const int row = wave * 32 + (j & 3) * 8 + rr;
+        const int row = isx ? wave * 32 + j * 8 + rr : wave * kWRows + (j - 4) * 8 + rr;
         const int32_t g = isx ? min(n0 + row, N - 1) : min(k0 + row, K - 1);
         src[j] = (isx ? X : W) + (size_t)g * D + d0 + 4 * swz(row, pos);
+        dst[j] = isx ? (wave * 32 + j * 8) * kSlice : kTM * kSlice + (wave * kWRows + (j - 4) * 8) * kSlice;
     }
     auto copy = [&](int st) {
         uint8_t *stage = lds + (st % kRingN) * kStage;
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            __builtin_amdgcn_global_load_lds(
-                (glb_void_t *)(src[j] + st * (kSlice / 4)),
-                (lds_void_t *)(stage + (j < 4 ? 0 : kT * kSlice) + (wave * 32 + (j & 3) * 8) * kSlice),
-                16, 0, 0);
+        for (int j = 0; j < kCopies; ++j)
+            __builtin_amdgcn_global_load_lds((glb_void_t *)(src[j] + st * (kSlice / 4)),
+                                             (lds_void_t *)(stage + dst[j]), 16, 0, 0);
     };
 
     const int fr = lane & 31, fq = lane >> 5;
-    int oa[2][4], ob[2][4];
+    int oa[2][4], ob[kJB][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int ra = wm * 64 + 32 * i + fr, rb = wn * 64 + 32 * i + fr;
+    for (int p = 0; p < 4; ++p) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int i = 0; i < 2; ++i) {
+            const int ra = wm * 64 + 32 * i + fr;
             oa[i][p] = ra * kSlice + 16 * swz(ra, 2 * p + fq);
-            ob[i][p] = kT * kSlice + rb * kSlice + 16 * swz(rb, 2 * p + fq);
+        }
+#pragma unroll
+        for (int j = 0; j < kJB; ++j) {
+            const int rb = wn * (kTK / 2) + 32 * j + fr;
+            ob[j][p] = kTM * kSlice + rb * kSlice + 16 * swz(rb, 2 * p + fq);
         }
     }
-    typedef floatx4 Frag[2][4];
-    auto read = [&](int st, Frag &a, Frag &b) {
+    struct Frag {
+        floatx4 a[2][4], b[kJB][4];
+    };
+    auto read = [&](int st, Frag &f) {
         const uint8_t *stage = lds + (st % kRingN) * kStage;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int p = 0; p < 4; ++p) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                a[i][p] = *reinterpret_cast<const floatx4 *>(stage + oa[i][p]);
-                b[i][p] = *reinterpret_cast<const floatx4 *>(stage + ob[i][p]);
-            }
+            for (int i = 0; i < 2; ++i)
+                f.a[i][p] = *reinterpret_cast<const floatx4 *>(stage + oa[i][p]);
+#pragma unroll
+            for (int j = 0; j < kJB; ++j)
+                f.b[j][p] = *reinterpret_cast<const floatx4 *>(stage + ob[j][p]);
+        }
     };
-    floatx16 acc[2][2] = {{{}, {}}, {{}, {}}};
-    auto mma = [&](const Frag &a, const Frag &b) {
+    floatx16 acc[2][kJB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < kJB; ++j) acc[i][j] = floatx16{};
+    auto mma = [&](const Frag &f) {
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -284,45 +302,45 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][p][c], b[j][p][c],
+                    for (int j = 0; j < kJB; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[i][p][c], f.b[j][p][c],
                                                                           acc[i][j], 0, 0, 0);
     };
     // Stage st's buffer is free once its fragments are in registers (read
     // during the previous step, before this step's barrier), so the copy of
     // stage st + kRingN goes there: kRingN - 1 stages stay in flight.
-    auto step = [&](int st, const Frag &ca, const Frag &cb, Frag &na, Frag &nb) {
-        wait_stage<8>(min(nst - 2 - st, kRingN - 2));
+    auto step = [&](int st, const Frag &cur, Frag &nxt) {
+        wait_stage<kCopies>(min(nst - 2 - st, kRingN - 2));
         barrier_lds();
         if (st + kRingN < nst) copy(st + kRingN);
-        read(st + 1, na, nb);
-        mma(ca, cb);
+        read(st + 1, nxt);
+        mma(cur);
     };
 #pragma unroll
     for (int st = 0; st < kRingN; ++st)
         if (st < nst) copy(st);
-    Frag a0, b0, a1, b1;
-    wait_stage<8>(min(nst - 1, kRingN - 1));
+    Frag f0, f1;
+    wait_stage<kCopies>(min(nst - 1, kRingN - 1));
     barrier_lds();
-    read(0, a0, b0);
+    read(0, f0);
     int st = 0;
     for (; st + 2 < nst; st += 2) {
-        step(st, a0, b0, a1, b1);
-        step(st + 1, a1, b1, a0, b0);
+        step(st, f0, f1);
+        step(st + 1, f1, f0);
     }
     if (st + 1 < nst) {
-        step(st, a0, b0, a1, b1);
-        mma(a1, b1);
+        step(st, f0, f1);
+        mma(f1);
     } else {
-        mma(a0, b0);
+        mma(f0);
     }
 
     // 32 x 32 block layout: register r of lane l is row 8 (r / 4) + 4 (l / 32)
     // + r % 4, column l % 32.
     auto for_each = [&](auto &&f) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int32_t k = k0 + wn * 64 + 32 * j + (lane & 31);
+        for (int j = 0; j < kJB; ++j) {
+            const int32_t k = k0 + wn * (kTK / 2) + 32 * j + (lane & 31);
             if (k >= K) continue;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -384,8 +402,13 @@ __global__ __launch_bounds__(256) void k_reduce_argmax(const float *__restrict__
 
 }  // namespace
 
+// Identities per tile of the split kernel. On the 4096 x 256 x 7552 product
+// 128 (64 tiles, D split in 4) ran in 164 us and 64 (128 tiles, D split in 2)
+// in 171-176 us.
+constexpr int kSplitTK = 128;
+
 int32_t score_f32_splits(int32_t N, int32_t K, int32_t D, int32_t num_cus, size_t part_elems) {
-    const int64_t tiles = (int64_t)((N + 127) / 128) * ((K + 127) / 128);
+    const int64_t tiles = (int64_t)((N + 127) / 128) * ((K + kSplitTK - 1) / kSplitTK);
     int32_t best = 1;
     for (int32_t sp = 2; sp <= 4; sp *= 2) {
         if (tiles * best >= num_cus) break;  // enough workgroups already
@@ -402,9 +425,9 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
     if (N <= 0 || K <= 0) return hipSuccess;
     const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
     if (aligned && splits >= 1 && D % (32 * splits) == 0 && (splits == 1 || part)) {
-        dim3 g((N + 127) / 128, (K + 127) / 128, splits);
-        hipLaunchKernelGGL(k_score_f32_split<4>, g, dim3(256), 0, s, X, N, W, b, K, D, S, splits,
-                           part);
+        dim3 g((N + 127) / 128, (K + kSplitTK - 1) / kSplitTK, splits);
+        hipLaunchKernelGGL((k_score_f32_split<4, kSplitTK>), g, dim3(256), 0, s, X, N, W, b, K, D,
+                           S, splits, part);
         if (splits > 1) {
             hipLaunchKernelGGL(k_reduce_argmax, dim3((N + 3) / 4), dim3(256), 0, s, part, splits,
                                N, K, b, S, argmax);
