@@ -258,9 +258,9 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
 
 // --- GEMM, large tiles ----------------------------------------------------------
 //
-// A workgroup of 4 waves owns a 256 (n) x 256 (k) tile of S; wave (wm, wn)
-// owns rows 128 wm .. +128 and columns 128 wn .. +128 as 4 x 4 blocks of
-// 32 x 32. The reduction dimension advances in stages of 64 bytes per row
+// A workgroup of kW waves owns a 256 (n) x 256 (k) tile of S; wave (wm, wn)
+// owns rows 128 wm .. +128 and columns (256 / (kW / 2)) wn .. as 4 x (8 / kW * 2)
+// blocks of 32 x 32 (4 waves: 4 x 4 blocks; 8 waves: 4 x 2). The reduction dimension advances in stages of 64 bytes per row
 // through a ring of kStages LDS buffers (32 KB each: A 256 rows, B 256 rows).
 // Stages are copied with global_load_lds_dwordx4 (global -> LDS without
 // registers): each wave instruction fills 1 KB = 16 rows of 64 bytes, lane i
@@ -275,6 +275,9 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
 constexpr int kBigT = 256;      // tile rows and columns
 constexpr int kStageB = 64;     // bytes of the reduction per row and stage
 constexpr int kStages = 5;  // 5 x 32 KB: all of the 160 KB LDS
+// Waves per 256 x 256 workgroup (4 or 8). On 32768 x 8192 x 7552, quantisation
+// included: 8 waves BF16 827 TFLOP/s, FP8 1278; 4 waves 784 and 1182.
+constexpr int kBigWaves = 8;
 constexpr int kStageBytes = 2 * kBigT * kStageB;  // A then B
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -301,41 +304,51 @@ __device__ __forceinline__ void barrier_lds() {
     asm volatile("" ::: "memory");
 }
 
-// Copy stage kb (byte offset into every row) into LDS buffer `buf`.
-// Rows past the matrix end re-read its last row (their results are dropped).
+// Copy stage kb (byte offset into every row) into LDS buffer `buf`; with kW
+// waves each copies 256 / kW rows of A and of B (1 KB = 16 rows per
+// instruction). Rows past the matrix end re-read its last row (their results
+// are dropped).
+template <int kW>
 __device__ __forceinline__ void copy_stage(const uint8_t *__restrict__ Xq, int32_t N, int32_t n0,
                                            const uint8_t *__restrict__ Wq, int32_t K, int32_t k0,
                                            int32_t pitch, int32_t kb, uint8_t *buf, int wave,
                                            int lane) {
+    constexpr int kPer = kBigT / kW / 16;  // instructions per wave and matrix
     const int r_in = lane >> 2, pos = lane & 3;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int r = (wave * 4 + j) * 16 + r_in;  // 0..255
+    for (int j = 0; j < kPer; ++j) {
+        const int r = (wave * kPer + j) * 16 + r_in;  // 0..255
         const int c = swz(r, pos);
         const int32_t n = min(n0 + r, N - 1);
         const uint8_t *src = Xq + (size_t)n * pitch + kb + 16 * c;
         __builtin_amdgcn_global_load_lds((glb_void_t *)src,
-                                         (lds_void_t *)(buf + (wave * 4 + j) * 1024), 16, 0, 0);
+                                         (lds_void_t *)(buf + (wave * kPer + j) * 1024), 16, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int r = (wave * 4 + j) * 16 + r_in;
+    for (int j = 0; j < kPer; ++j) {
+        const int r = (wave * kPer + j) * 16 + r_in;
         const int c = swz(r, pos);
         const int32_t k = min(k0 + r, K - 1);
         const uint8_t *src = Wq + (size_t)k * pitch + kb + 16 * c;
         __builtin_amdgcn_global_load_lds(
-            (glb_void_t *)src, (lds_void_t *)(buf + kBigT * kStageB + (wave * 4 + j) * 1024), 16,
-            0, 0);
+            (glb_void_t *)src, (lds_void_t *)(buf + kBigT * kStageB + (wave * kPer + j) * 1024),
+            16, 0, 0);
     }
 }
 
-template <int kMode>
-__global__ __launch_bounds__(256) void k_score_lp_big(const uint8_t *__restrict__ Xq,
-                                                      const float *__restrict__ sx, int32_t N,
-                                                      const uint8_t *__restrict__ Wq,
-                                                      const float *__restrict__ sw,
-                                                      const float *__restrict__ bias, int32_t K,
-                                                      int32_t pitch, float *__restrict__ S) {
+// kW waves (4: one per SIMD, each 128 x 128 of the tile; 8: two per SIMD,
+// each 128 x 64, so one wave's waits are covered by the other's MFMAs).
+template <int kMode, int kW>
+__global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restrict__ Xq,
+                                                          const float *__restrict__ sx, int32_t N,
+                                                          const uint8_t *__restrict__ Wq,
+                                                          const float *__restrict__ sw,
+                                                          const float *__restrict__ bias,
+                                                          int32_t K, int32_t pitch,
+                                                          float *__restrict__ S) {
+    constexpr int kCW = kBigT / (kW / 2);  // identities per wave
+    constexpr int kJB = kCW / 32;          // 32-wide blocks per wave
+    constexpr int kCopies = 2 * (kBigT / kW / 16);
     __shared__ __attribute__((aligned(1024))) uint8_t lds[kStages * kStageBytes];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -350,41 +363,47 @@ __global__ __launch_bounds__(256) void k_score_lp_big(const uint8_t *__restrict_
     const int32_t n0 = (int32_t)(g * kGroupN + i_g % gn) * kBigT;
     const int32_t k0 = (int32_t)(i_g / gn) * kBigT;
 
-    f32x16 acc[4][4];
+    f32x16 acc[4][kJB];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x16{};
+        for (int j = 0; j < kJB; ++j) acc[i][j] = f32x16{};
 
     const int nst = pitch / kStageB;
     const int fr = lane & 31, fq = lane >> 5;
     // Fragments of one stage: [block][h]. BF16/FP16: h = the 32-byte sub-step
     // (this lane's 16 bytes of it); FP8: the two 16-byte halves of this lane's
     // 32 bytes of the single 64-byte step.
-    auto read = [&](int st, u32x4 (&a)[4][2], u32x4 (&b)[4][2]) {
+    struct Frag {
+        u32x4 a[4][2], b[kJB][2];
+    };
+    auto read = [&](int st, Frag &f) {
         const uint8_t *bufA = lds + (st % kStages) * kStageBytes;
         const uint8_t *bufB = bufA + kBigT * kStageB;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ra = wm * 128 + 32 * i + fr;
-            const int rb = wn * 128 + 32 * i + fr;
+        for (int h = 0; h < 2; ++h) {
+            const int c = (kMode == LBPF_FP8_E4M3) ? 2 * fq + h : 2 * h + fq;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int c = (kMode == LBPF_FP8_E4M3) ? 2 * fq + h : 2 * h + fq;
-                a[i][h] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, c));
-                b[i][h] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, c));
+            for (int i = 0; i < 4; ++i) {
+                const int ra = wm * 128 + 32 * i + fr;
+                f.a[i][h] = *reinterpret_cast<const u32x4 *>(bufA + ra * kStageB + 16 * swz(ra, c));
+            }
+#pragma unroll
+            for (int j = 0; j < kJB; ++j) {
+                const int rb = wn * kCW + 32 * j + fr;
+                f.b[j][h] = *reinterpret_cast<const u32x4 *>(bufB + rb * kStageB + 16 * swz(rb, c));
             }
         }
     };
-    auto mma = [&](const u32x4 (&a)[4][2], const u32x4 (&b)[4][2]) {
+    auto mma = [&](const Frag &f) {
         constexpr int kSubs = (kMode == LBPF_FP8_E4M3) ? 1 : 2;
 #pragma unroll
         for (int sub = 0; sub < kSubs; ++sub)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = mfma_step<kMode>(a[i], b[j], acc[i][j], sub);
+                for (int j = 0; j < kJB; ++j)
+                    acc[i][j] = mfma_step<kMode>(f.a[i], f.b[j], acc[i][j], sub);
     };
     // Iteration st: make stage st + 1 visible, start copying stage
     // st + kStages - 1 into the buffer of stage st - 1 (read an iteration
@@ -395,47 +414,67 @@ __global__ __launch_bounds__(256) void k_score_lp_big(const uint8_t *__restrict_
     // previous step, before this step's barrier), so the copy of stage
     // st + kStages goes there: kStages - 1 stages stay in flight.
     auto wait_younger = [](int younger) {
-        if (younger >= 4) wait_vm<8 * 4>();
-        else if (younger == 3) wait_vm<8 * 3>();
-        else if (younger == 2) wait_vm<8 * 2>();
-        else if (younger == 1) wait_vm<8>();
+        if (younger >= 4) wait_vm<kCopies * 4>();
+        else if (younger == 3) wait_vm<kCopies * 3>();
+        else if (younger == 2) wait_vm<kCopies * 2>();
+        else if (younger == 1) wait_vm<kCopies>();
         else wait_vm<0>();
     };
-    auto step = [&](int st, const u32x4 (&ca)[4][2], const u32x4 (&cb)[4][2], u32x4 (&na)[4][2],
-                    u32x4 (&nb)[4][2]) {
+    auto step = [&](int st, const Frag &cur, Frag &nxt) {
         wait_younger(min(nst - 2 - st, kStages - 2));
         barrier_lds();
         if (st + kStages < nst)
-            copy_stage(Xq, N, n0, Wq, K, k0, pitch, (st + kStages) * kStageB,
-                       lds + (st % kStages) * kStageBytes, wave, lane);
-        read(st + 1, na, nb);
-        mma(ca, cb);
+            copy_stage<kW>(Xq, N, n0, Wq, K, k0, pitch, (st + kStages) * kStageB,
+                           lds + (st % kStages) * kStageBytes, wave, lane);
+        read(st + 1, nxt);
+        mma(cur);
     };
 #pragma unroll
     for (int st = 0; st < kStages; ++st)
-        if (st < nst) copy_stage(Xq, N, n0, Wq, K, k0, pitch, st * kStageB, lds + st * kStageBytes,
-                                 wave, lane);
+        if (st < nst)
+            copy_stage<kW>(Xq, N, n0, Wq, K, k0, pitch, st * kStageB, lds + st * kStageBytes,
+                           wave, lane);
+    if constexpr (kW == 8) {
+        // Two waves per SIMD: fragments single-buffered (the registers go to
+        // the accumulators), the other wave's MFMAs cover the LDS reads.
+        // Stage st's buffer is refilled one step later, after the barrier
+        // that follows its reads.
+        Frag f;
+        for (int st = 0; st < nst; ++st) {
+            // Issued so far: stages 0 .. kStages - 1, then one per earlier
+            // iteration j >= 1 (stage j - 1 + kStages): younger than st are
+            // kStages - 1 stages at st = 0 and kStages - 2 after that.
+            wait_younger(min(nst - 1 - st, st == 0 ? kStages - 1 : kStages - 2));
+            barrier_lds();
+            if (st >= 1 && st - 1 + kStages < nst)
+                copy_stage<kW>(Xq, N, n0, Wq, K, k0, pitch, (st - 1 + kStages) * kStageB,
+                               lds + ((st - 1) % kStages) * kStageBytes, wave, lane);
+            read(st, f);
+            mma(f);
+        }
+    } else {
     wait_younger(min(nst - 1, kStages - 1));
     barrier_lds();
-    u32x4 a0[4][2], b0[4][2], a1[4][2], b1[4][2];
-    read(0, a0, b0);
+    Frag f0, f1;
+    read(0, f0);
     int st = 0;
     for (; st + 2 < nst; st += 2) {
-        step(st, a0, b0, a1, b1);
-        step(st + 1, a1, b1, a0, b0);
+        step(st, f0, f1);
+        step(st + 1, f1, f0);
     }
     if (st + 1 < nst) {  // two stages left
-        step(st, a0, b0, a1, b1);
-        mma(a1, b1);
+        step(st, f0, f1);
+        mma(f1);
     } else {
-        mma(a0, b0);
+        mma(f0);
+    }
     }
 
     // 32 x 32 block layout: lane l, register r holds row 8 (r / 4) + 4 (l / 32)
     // + r % 4 and column l % 32.
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int32_t k = k0 + wn * 128 + 32 * j + (lane & 31);
+    for (int j = 0; j < kJB; ++j) {
+        const int32_t k = k0 + wn * kCW + 32 * j + (lane & 31);
         if (k >= K) continue;
         const float swk = sw[k], bk = bias[k];
 #pragma unroll
@@ -479,15 +518,16 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
     if (N >= 2 * kBigT && K >= kBigT) {
         // Large products: 256 x 256 tiles fed through the LDS ring.
         dim3 grid(((K + kBigT - 1) / kBigT) * ((N + kBigT - 1) / kBigT));
+        constexpr int kW = kBigWaves;
         if (mode == LBPF_BF16)
-            hipLaunchKernelGGL(k_score_lp_big<LBPF_BF16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw,
-                               b, K, pitch, S);
+            hipLaunchKernelGGL((k_score_lp_big<LBPF_BF16, kW>), grid, dim3(64 * kW), 0, s, Xq, sx,
+                               N, Wq, sw, b, K, pitch, S);
         else if (mode == LBPF_FP16)
-            hipLaunchKernelGGL(k_score_lp_big<LBPF_FP16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw,
-                               b, K, pitch, S);
+            hipLaunchKernelGGL((k_score_lp_big<LBPF_FP16, kW>), grid, dim3(64 * kW), 0, s, Xq, sx,
+                               N, Wq, sw, b, K, pitch, S);
         else
-            hipLaunchKernelGGL(k_score_lp_big<LBPF_FP8_E4M3>, grid, dim3(256), 0, s, Xq, sx, N, Wq,
-                               sw, b, K, pitch, S);
+            hipLaunchKernelGGL((k_score_lp_big<LBPF_FP8_E4M3, kW>), grid, dim3(64 * kW), 0, s, Xq,
+                               sx, N, Wq, sw, b, K, pitch, S);
         return hipGetLastError();
     }
     dim3 grid(((K + kTN - 1) / kTN) * ((N + kTM - 1) / kTM));
