@@ -41,10 +41,13 @@
  *     coexist. Work may be queued on several streams through one context:
  *     lbpf_features stages box tables through a small ring of buffers (it
  *     waits for the oldest slot before reusing it), and lbpf_score calls that
- *     use the context's scratch (reduced precision, or argmax without caller
- *     scores) are ordered across streams by an event the context keeps, so
- *     they never overlap each other; everything else may overlap. Inside a
- *     captured graph that ordering is the graph's.
+ *     use the context's scratch (reduced precision, argmax without caller
+ *     scores, or FP32 products too small to fill the GPU, whose feature
+ *     dimension is split over workgroups) are ordered across streams by an
+ *     event the context keeps, so they never overlap each other; everything
+ *     else may overlap. Inside a captured graph that ordering is the graph's,
+ *     and a graph replay must not overlap eager scoring through the same
+ *     context.
  */
 #ifndef LBPF_H
 #define LBPF_H
@@ -299,9 +302,12 @@ int32_t lbpf_weights_count(const lbpf_weights *weights);
 /* Score N feature rows against every enrolled identity (step 6).
  * hist: DEVICE [N][D] FP32. scores_opt: DEVICE [N][K] FP32 or NULL.
  * argmax_opt: DEVICE [N] int32 or NULL (not both NULL). N = 0 is a no-op.
- * In FP32 the scores are accumulated in FP32 by MFMA; in the reduced
- * precisions the operands are converted as documented for lbpf_precision and
- * the products accumulated in FP32. Errors: LBPF_E_INVALID, LBPF_E_HIP. */
+ * In FP32 the scores are accumulated in FP32 by MFMA (when the product has
+ * too few 128 x 128 output tiles to fill the GPU, the feature dimension is
+ * split into up to 4 equal ranges whose partial sums are added in range
+ * order, so results are deterministic); in the reduced precisions the
+ * operands are converted as documented for lbpf_precision and the products
+ * accumulated in FP32. Errors: LBPF_E_INVALID, LBPF_E_HIP. */
 lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_weights *weights,
                        float *scores_opt, int32_t *argmax_opt, void *stream);
 
