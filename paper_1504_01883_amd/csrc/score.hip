@@ -366,6 +366,9 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
 // Split-D epilogue, one wave per row: S = (((part_0 + part_1) + ...) + b in
 // split order, and (optionally) the row's argmax, ties to the lowest index as
 // in k_argmax.
+// kVec: K a multiple of 4 and 16-byte aligned rows, so each lane takes four
+// consecutive identities per step as float4.
+template <bool kVec>
 __global__ __launch_bounds__(256) void k_reduce_argmax(const float *__restrict__ part,
                                                        int32_t splits, int32_t N, int32_t K,
                                                        const float *__restrict__ bias,
@@ -377,14 +380,30 @@ __global__ __launch_bounds__(256) void k_reduce_argmax(const float *__restrict__
     const size_t plane = (size_t)N * K, row = (size_t)n * K;
     float best = -INFINITY;
     int32_t arg = K;
-    for (int32_t k = lane; k < K; k += 64) {
-        float v = part[row + k];
-        for (int q = 1; q < splits; ++q) v += part[(size_t)q * plane + row + k];
-        v += bias[k];
-        S[row + k] = v;
-        if (v > best || arg == K) {
-            best = v;
-            arg = k;
+    if constexpr (kVec) {
+        for (int32_t k = 4 * lane; k < K; k += 256) {
+            floatx4 v = *reinterpret_cast<const floatx4 *>(part + row + k);
+            for (int q = 1; q < splits; ++q)
+                v += *reinterpret_cast<const floatx4 *>(part + (size_t)q * plane + row + k);
+            v += *reinterpret_cast<const floatx4 *>(bias + k);
+            *reinterpret_cast<floatx4 *>(S + row + k) = v;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)  // k + c ascending: a strict > keeps the first
+                if (v[c] > best || arg == K) {
+                    best = v[c];
+                    arg = k + c;
+                }
+        }
+    } else {
+        for (int32_t k = lane; k < K; k += 64) {
+            float v = part[row + k];
+            for (int q = 1; q < splits; ++q) v += part[(size_t)q * plane + row + k];
+            v += bias[k];
+            S[row + k] = v;
+            if (v > best || arg == K) {
+                best = v;
+                arg = k;
+            }
         }
     }
     if (!out) return;
@@ -429,8 +448,13 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
         hipLaunchKernelGGL((k_score_f32_split<4, kSplitTK>), g, dim3(256), 0, s, X, N, W, b, K, D,
                            S, splits, part);
         if (splits > 1) {
-            hipLaunchKernelGGL(k_reduce_argmax, dim3((N + 3) / 4), dim3(256), 0, s, part, splits,
-                               N, K, b, S, argmax);
+            const bool v4 = K % 4 == 0 && ((uintptr_t)S % 16 == 0) && ((uintptr_t)b % 16 == 0);
+            if (v4)
+                hipLaunchKernelGGL(k_reduce_argmax<true>, dim3((N + 3) / 4), dim3(256), 0, s, part,
+                                   splits, N, K, b, S, argmax);
+            else
+                hipLaunchKernelGGL(k_reduce_argmax<false>, dim3((N + 3) / 4), dim3(256), 0, s,
+                                   part, splits, N, K, b, S, argmax);
             return hipGetLastError();
         }
         hipError_t e = hipGetLastError();
