@@ -13,7 +13,11 @@ outputs rotate so the 256 MB last-level cache cannot serve repeats.
 
 Prints one JSON line (rank 0). Extra objects: `roofline` for the dominant
 kernel (HIP-event durations over the timed region), `kernels` for every
-kernel of the step, and `cpu_baseline` (the CPU oracle on the host cores).
+kernel of the step, `plain_gpu_path` (the unbatched comparator's crops/s),
+`latency` (p50/p99 frame latency of a short serving run, fused and plain) and
+`cpu_baseline` (the CPU oracle on the host cores, with the GPU line's stated
+accuracy: FP32 score error against the oracle's FP64 scores and argmax
+agreement).
 """
 from __future__ import annotations
 
@@ -43,6 +47,9 @@ def _parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-latency", action="store_true",
+                   help="skip the short serving run that gives p50/p99 frame latency")
+    p.add_argument("--latency-seconds", type=float, default=3.0)
     p.add_argument("--cpu-sample", type=int, default=4096,
                    help="crops of the workload the CPU oracle is timed on")
     p.add_argument("--plain-sample", type=int, default=512,
@@ -199,10 +206,16 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(grey, depth, W, b, argmax.cpu().numpy(), args.cpu_sample)
+        cpu = cpu_baseline(grey, depth, W, b, argmax.cpu().numpy(), scores.cpu().numpy(),
+                           args.cpu_sample)
+
+    latency = None
+    if not args.no_latency:
+        from paper_1504_01883_amd import serve
+        latency = serve.quick_latency(ctx, seconds=args.latency_seconds)
 
     out = {
-        "metric": "face crops/s (LBP+hist+SVM)",
+        "metric": "face crops/s (LBP+hist+SVM) vs plain GPU path at stated acc.; p50/p99 latency",
         "value": N_CROPS / (ms_step * 1e-3),
         "unit": "crops/s",
         "n_gpus": 1,
@@ -222,6 +235,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "plain_gpu_path": plain,
+        "latency": latency,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -531,9 +545,11 @@ def plain_path(ctx, plane, wts, sample, fused_ms_step):
             "fused_speedup": fused / rate}
 
 
-def cpu_baseline(grey, depth, W, b, gpu_argmax, sample):
+def cpu_baseline(grey, depth, W, b, gpu_argmax, gpu_scores, sample):
     """The CPU oracle (unchanged) on a bounded sample of the same workload:
-    features + FP64 scores + argmax, all host threads."""
+    features + FP64 scores + argmax, all host threads. The stated accuracy of
+    the GPU line comes from the same run: the FP32 scores' largest error
+    relative to the dot product's condition scale, and argmax agreement."""
     import oracle
     n = min(sample, grey.shape[0])
     threads = min(16, os.cpu_count() or 1)
@@ -542,14 +558,25 @@ def cpu_baseline(grey, depth, W, b, gpu_argmax, sample):
     boxes[:, 2] = np.arange(n) * SIDE
     boxes[:, 3] = SIDE
     boxes[:, 4] = SIDE
+    # The whole sample is repeated until at least 10 s of host work has run,
+    # so the rate is not one short pass (each pass recomputes everything).
     t0 = time.perf_counter()
-    f, _, _ = oracle.features(hp, boxes, n_threads=threads)
-    _, am = oracle.score_f64(f, W, b, want_scores=False, n_threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "crops/s", "cores": threads, "kind": "oracle",
+    passes = 0
+    while True:
+        f, _, _ = oracle.features(hp, boxes, n_threads=threads)
+        s64, am = oracle.score_f64(f, W, b, want_scores=True, n_threads=threads)
+        passes += 1
+        dt = time.perf_counter() - t0
+        if dt >= 10.0 or passes >= 40:
+            break
+    scale = np.abs(f.astype(np.float64)) @ np.abs(W.astype(np.float64)).T + \
+        np.abs(b.astype(np.float64))[None, :]
+    err = float((np.abs(gpu_scores[:n].astype(np.float64) - s64) / scale).max())
+    return {"value": passes * n / dt, "unit": "crops/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of the {N_CROPS} crops, features + FP64 scores + argmax, "
-                      f"{dt:.1f} s",
-            "argmax_agreement_with_gpu": float((am == gpu_argmax[:n]).mean())}
+                      f"{passes} passes in {dt:.1f} s",
+            "argmax_agreement_with_gpu": float((am == gpu_argmax[:n]).mean()),
+            "max_score_err_over_condition_scale": err, "score_tolerance": 1e-5}
 
 
 if __name__ == "__main__":

@@ -330,6 +330,41 @@ def summarize(measured, wall: float) -> dict:
             "max_ms": float(lat.max())}
 
 
+def quick_latency(ctx, seconds: float = 3.0, warmup: float = 0.5) -> dict:
+    """A short run of the serving workload (16 streams x 30 fps, BF16 scores
+    against 1024 identities) for the headline line: p50/p99 frame latency of
+    the fused path and of the plain unbatched FP32 path on the same arrivals."""
+    import torch
+
+    from . import synth
+    n_streams, fps, K, pool = 16, 30.0, 1024, 8
+    W, b = synth.synthetic_weights(K, ctx.dim, synth.W_SERVING)
+    Wd, bd = torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda()
+    w_bf16 = ctx.weights(Wd, bd, precision="bf16")
+    w_fp32 = ctx.weights(Wd, bd, precision="fp32")
+    arr = poisson_arrivals(n_streams, fps, warmup + seconds, synth.SEED)
+    raw = {}
+    for (_, s, i) in arr:
+        if (s, i % pool) not in raw:
+            raw[(s, i % pool)] = synth.make_frame(s, i % pool, K)
+    out = {"workload": f"serving: {n_streams} streams x {fps:.0f} fps Poisson, 640x480 frames, "
+                       f"1-8 faces, {K} identities, {seconds:.0f} s measured"}
+    for name, wts, plain in (("fused_bf16", w_bf16, False), ("plain_unbatched_fp32", w_fp32, True)):
+        be = GpuBackend(ctx, wts, 128, 64, inflight=2, plain=plain)
+        frames = {}
+        for (_, s, i) in arr:
+            g, z, bx, ids = raw[(s, i % pool)]
+            frames[(s, i)] = (be.host_frame(g, z), bx, ids)
+        sch = Scheduler(128, 128 * FRAME_BYTES, max_batch_frames=64)
+        measured, wall, _ = run(be, sch, arr, frames, warmup)
+        summ = summarize(measured, wall)
+        out[name] = {k: summ[k] for k in ("frames", "crops_per_s", "p50_ms", "p99_ms")
+                     if k in summ}
+    w_bf16.close()
+    w_fp32.close()
+    return out
+
+
 def bench(args) -> dict:
     """Serving workload: 16 streams x 30 fps Poisson arrivals, 640x480 frames with
     1-8 faces, BF16 scoring against 1024 identities; 2 s warm-up + 30 s
