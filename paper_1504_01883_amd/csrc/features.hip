@@ -154,7 +154,7 @@ __device__ __forceinline__ void load8(const uint16_t *row, int x0, int w, uint32
 
 // Exact lower median of the non-zero depth values of the crop, -1 if none.
 // All threads of the block call it.
-__device__ int32_t crop_median(const CropDesc &c, MedianScratch &ms) {
+__device__ __noinline__ int32_t crop_median(const CropDesc c, MedianScratch &ms) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cpr = (c.w + 7) >> 3;              // 8-pixel chunks per row (<= 128)
     const int rows_par = kThreads / cpr;         // rows visited in parallel
@@ -231,13 +231,17 @@ __device__ __forceinline__ uint32_t lbp_code(const T *p, int32_t pitch, int y, i
 
 // Per-pixel histogram loop for any crop and configuration: each thread takes
 // pixels in row order and increments its bins with LDS atomics.
-__device__ void lbp_hist_generic(const CropDesc &c, const FeatParams &fp, int32_t m,
+// With `packed` (both channels in use) the counters are the fast path's: one
+// word per (cell, bin), grey count in the low half, depth count in the high.
+template <int kNW = kWaves>
+__device__ void lbp_hist_generic(const CropDesc c, const FeatParams &fp, int32_t m,
                                  const uint8_t *sh_bin, const uint8_t *sh_rowband,
-                                 const uint8_t *sh_colband, uint32_t *sh_hist) {
+                                 const uint8_t *sh_colband, uint32_t *sh_hist,
+                                 bool packed = false) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cells = fp.grid_x * fp.grid_y;
     const int nb = fp.nbins;
-    for (int y = 1 + wave; y <= c.h - 2; y += kWaves) {
+    for (int y = 1 + wave; y <= c.h - 2; y += kNW) {
         const int rowcell = sh_rowband[y] * fp.grid_x;
         for (int x = 1 + lane; x <= c.w - 2; x += 64) {
             const uint32_t dc = c.depth[(size_t)y * c.depth_pitch + x];
@@ -251,7 +255,10 @@ __device__ void lbp_hist_generic(const CropDesc &c, const FeatParams &fp, int32_
             }
             if (fp.use_depth) {
                 const uint32_t code = lbp_code(c.depth, c.depth_pitch, y, x);
-                atomicAdd(&sh_hist[(ch * cells + cell) * nb + sh_bin[code]], 1u);
+                if (packed)
+                    atomicAdd(&sh_hist[cell * nb + sh_bin[code]], 0x10000u);
+                else
+                    atomicAdd(&sh_hist[(ch * cells + cell) * nb + sh_bin[code]], 1u);
             }
         }
     }
@@ -269,6 +276,13 @@ __device__ __forceinline__ T gld(const void *base, uint32_t byte_off) {
     return *(const gT *)((const __attribute__((address_space(1))) char *)base + byte_off);
 }
 
+// Streaming (non-temporal) store: the feature rows are not read again by this
+// kernel, and kept out of L2's reuse they do not evict the depth lines that
+// the code pass reads a second time.
+template <typename T>
+__device__ __forceinline__ void st_nt(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
 // (a & m) | c with m in an SGPR: one VALU instruction (gfx9 VOP3 takes no
 // literal, so the compiler would otherwise split it into AND + OR).
 __device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t m, uint32_t c) {
@@ -325,6 +339,68 @@ __device__ __forceinline__ uint32_t wave_sort64(uint32_t x, int lane) {
     return x;
 }
 
+// One u16 pair of the median pass: per-half counts of v >= lo (ge2) and of
+// v != 0 (nz2), and the 1 mm window histogram of [lo, lo + 256). one2 holds
+// 0x10001 (kept opaque to the compiler, see crop_median_fast).
+__device__ __forceinline__ void median_count(uint32_t q, uint32_t lolo, uint32_t lm1,
+                                             uint32_t one2, uint32_t &ge2, uint32_t &nz2,
+                                             MedianScratch &ms) {
+    // v >= lo iff v - (lo - 1) saturates above 0 (lo >= 1, so 0 is not).
+    ge2 += pk_min(pk_sub_sat(q, lm1), one2);
+    nz2 += pk_min(q, one2);
+    const uint32_t t = pk_sub(q, lolo);  // v - lo; >= 256 for v = 0
+    const uint32_t t0 = t & 0xFFFFu, t1 = t >> 16;
+    if (t0 < 256u) atomicAdd(&ms.hist[t0], 1u);
+    if (t1 < 256u) atomicAdd(&ms.hist[t1], 1u);
+}
+
+// End of the median pass for a block of kNW waves: totals over the block,
+// then the lower median's rank looked up in the window histogram. Returns
+// the median, -1 when the crop has no depth, -2 when the median lies outside
+// [lo, lo + 256) (the caller then runs the exact radix select). All threads
+// call it; it ends with a barrier.
+template <int kNW>
+__device__ __forceinline__ int32_t median_finish(MedianScratch &ms, uint32_t *sh_red,
+                                                 uint32_t ge2, uint32_t nz2, int32_t lo) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nnz = wave_sum((nz2 & 0xFFFFu) + (nz2 >> 16));
+    const uint32_t below = nnz - wave_sum((ge2 & 0xFFFFu) + (ge2 >> 16));
+    if (lane == 0) {
+        sh_red[wave] = below;
+        sh_red[kNW + wave] = nnz;
+    }
+    __syncthreads();
+    uint32_t tb = 0, tn = 0;
+#pragma unroll
+    for (int i = 0; i < kNW; ++i) {
+        tb += sh_red[i];
+        tn += sh_red[kNW + i];
+    }
+    if (tn == 0) return -1;  // uniform: every thread sees the same totals
+    const uint32_t rank = (tn - 1) / 2;
+    if (wave == 0) {
+        if (rank >= tb) {
+            select_bin(ms, rank - tb, lane);  // -1 when the rank lies above the window
+        } else if (lane == 0) {
+            ms.bin = -1;
+        }
+    }
+    __syncthreads();
+    const int32_t bin = ms.bin;
+    __syncthreads();
+    (void)tid;
+    return bin >= 0 ? lo + bin : -2;
+}
+
+// The 64-sample estimate of the median (wave 0 only): the lower median of the
+// non-zero values among `v` (one per lane), or 1000 when all are zero.
+__device__ __forceinline__ uint32_t median_estimate(uint32_t v, int lane) {
+    const uint32_t sorted = wave_sort64(v ? v : 0x10000u, lane);  // zeros last
+    const int nz = __popcll(__ballot(v != 0));
+    const uint32_t est = __shfl(sorted, nz > 0 ? (nz - 1) / 2 : 0, 64);
+    return nz > 0 ? est : 1000u;
+}
+
 // Exact lower median of the crop's non-zero depth, -1 if none.
 //  1. Wave 0 estimates it: the lower median of the non-zero values among 64
 //     pixels on an 8 x 8 grid.
@@ -335,7 +411,8 @@ __device__ __forceinline__ uint32_t wave_sort64(uint32_t x, int lane) {
 //  3. When the median's rank falls inside the window, the window histogram
 //     gives it exactly; otherwise the two-level radix select runs.
 // All threads of the block call it.
-__device__ int32_t crop_median_fast(const CropDesc &c, MedianScratch &ms, uint32_t *sh_red) {
+__device__ __forceinline__ int32_t crop_median_fast(const CropDesc &c, MedianScratch &ms,
+                                                   uint32_t *sh_red) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cpr = (c.w + 7) >> 3;
     const int rows_par = kThreads / cpr;
@@ -352,18 +429,19 @@ __device__ int32_t crop_median_fast(const CropDesc &c, MedianScratch &ms, uint32
     if (wave == 0) {
         const int sy = ((2 * (lane >> 3) + 1) * c.h) >> 4;
         const int sx = ((2 * (lane & 7) + 1) * c.w) >> 4;
-        const uint32_t v = c.depth[(size_t)sy * c.depth_pitch + sx];
-        const uint32_t sorted = wave_sort64(v ? v : 0x10000u, lane);  // zeros last
-        const int nz = __popcll(__ballot(v != 0));
-        const uint32_t est = __shfl(sorted, nz > 0 ? (nz - 1) / 2 : 0, 64);
-        if (lane == 0) ms.rank = nz > 0 ? est : 1000u;
+        const uint32_t est = median_estimate(c.depth[(size_t)sy * c.depth_pitch + sx], lane);
+        if (lane == 0) ms.rank = est;
     }
     __syncthreads();
     const int32_t lo = min(max((int32_t)ms.rank - 128, 1), 65536 - 256);
     const uint32_t lolo = (uint32_t)lo * 0x10001u;
     const uint32_t lm1 = (uint32_t)(lo - 1) * 0x10001u;
+    // A 1 in each half that the compiler cannot see: with a visible constant
+    // it turns each packed min below into two compares and selects.
+    uint32_t one2 = 0x10001u;
+    asm volatile("" : "+s"(one2));
 
-    uint32_t below2 = 0, nz2 = 0;  // per-half counts
+    uint32_t ge2 = 0, nz2 = 0;  // per-half counts of v >= lo and of v != 0
     for (int kb = 0; kb < nk; kb += kMedBatch) {
         if (kb > 0) {
 #pragma unroll
@@ -374,83 +452,36 @@ __device__ int32_t crop_median_fast(const CropDesc &c, MedianScratch &ms, uint32
         for (int u = 0; u < kMedBatch; ++u) {
             if (kb + u >= nk) break;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t q = buf[u][i];
-                // below: 1 <= v < lo, i.e. v - 1 < lo - 1 (v = 0 wraps high).
-                below2 += pk_min(pk_sub_sat(lm1, pk_sub(q, 0x10001u)), 0x10001u);
-                nz2 += pk_min(q, 0x10001u);
-                const uint32_t t = pk_sub(q, lolo);  // v - lo; >= 256 for v = 0
-                const uint32_t t0 = t & 0xFFFFu, t1 = t >> 16;
-                if (t0 < 256u) atomicAdd(&ms.hist[t0], 1u);
-                if (t1 < 256u) atomicAdd(&ms.hist[t1], 1u);
-            }
+            for (int i = 0; i < 4; ++i) median_count(buf[u][i], lolo, lm1, one2, ge2, nz2, ms);
         }
     }
-    const uint32_t below = wave_sum((below2 & 0xFFFFu) + (below2 >> 16));
-    const uint32_t nnz = wave_sum((nz2 & 0xFFFFu) + (nz2 >> 16));
-    if (lane == 0) {
-        sh_red[wave] = below;
-        sh_red[kWaves + wave] = nnz;
-    }
-    __syncthreads();
-    uint32_t tb = 0, tn = 0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) {
-        tb += sh_red[i];
-        tn += sh_red[kWaves + i];
-    }
-    if (tn == 0) return -1;  // uniform: every thread sees the same totals
-    const uint32_t rank = (tn - 1) / 2;
-    if (wave == 0) {
-        if (rank >= tb) {
-            select_bin(ms, rank - tb, lane);  // -1 when the rank lies above the window
-        } else if (lane == 0) {
-            ms.bin = -1;
-        }
-    }
-    __syncthreads();
-    const int32_t bin = ms.bin;
-    __syncthreads();
-    if (bin >= 0) return lo + bin;
-    return crop_median(c, ms);
+    const int32_t r = median_finish<kWaves>(ms, sh_red, ge2, nz2, lo);
+    return r != -2 ? r : crop_median(c, ms);
 }
 
-// Columns x0..x0+3 of one row: grey bytes in G, depth u16 pairs in Z0
-// (x0, x0+1) and Z1 (x0+2, x0+3). With `full` the 4 columns are loaded as is
-// (columns past the crop are never used); otherwise they are clamped to w-1.
+// Columns x0..x0+3 of one row as loaded: grey bytes in G, depth u16 pairs
+// in Z0 (x0, x0+1) and Z1 (x0+2, x0+3). Every lane issues the same two loads,
+// from column xl = x0, or, for a lane that hangs over the right edge of a crop
+// that may not be over-read, from xl = w - 4; make_row then shifts that
+// lane's columns down by s = x0 - xl. Columns past the crop are never used.
 struct RawRow {
     uint32_t G, Z0, Z1;
 };
 
-__device__ __forceinline__ RawRow load_row(const CropDesc &c, int y, int x0, bool full) {
+__device__ __forceinline__ RawRow load_row(const CropDesc &c, int y, int xl) {
     RawRow r;
-    if (full) {
-        r.G = gld<uint32_t>(c.grey, (uint32_t)y * (uint32_t)c.grey_pitch + (uint32_t)x0);
-        const u32x2 z =
-            gld<u32x2>(c.depth, ((uint32_t)y * (uint32_t)c.depth_pitch + (uint32_t)x0) * 2u);
-        r.Z0 = z.x;
-        r.Z1 = z.y;
-    } else {
-        const uint8_t *grow = c.grey + (size_t)y * c.grey_pitch;
-        const uint16_t *drow = c.depth + (size_t)y * c.depth_pitch;
-        const int xa = min(x0, c.w - 1), x1 = min(x0 + 1, c.w - 1), x2 = min(x0 + 2, c.w - 1),
-                  x3 = min(x0 + 3, c.w - 1);
-        r.G = (uint32_t)grow[xa] | ((uint32_t)grow[x1] << 8) | ((uint32_t)grow[x2] << 16) |
-              ((uint32_t)grow[x3] << 24);
-        r.Z0 = (uint32_t)drow[xa] | ((uint32_t)drow[x1] << 16);
-        r.Z1 = (uint32_t)drow[x2] | ((uint32_t)drow[x3] << 16);
-    }
+    r.G = gld<uint32_t>(c.grey, (uint32_t)y * (uint32_t)c.grey_pitch + (uint32_t)xl);
+    const u32x2 z =
+        gld<u32x2>(c.depth, ((uint32_t)y * (uint32_t)c.depth_pitch + (uint32_t)xl) * 2u);
+    r.Z0 = z.x;
+    r.Z1 = z.y;
     return r;
 }
 
-// d' = 0 for d == 0, else clamp(d - lo, 0, span), on a pair of u16.
-__device__ __forceinline__ uint32_t to_window(uint32_t z, int32_t lo, uint32_t lolo, uint32_t span2) {
-    if (lo >= 0) return pk_min(pk_sub_sat(z, lolo), span2);
-    const uint32_t a = z & 0xFFFFu, b = z >> 16;
-    const int32_t span = (int32_t)(span2 & 0xFFFFu);
-    const uint32_t da = a ? (uint32_t)min((int32_t)a - lo, span) : 0u;
-    const uint32_t db = b ? (uint32_t)min((int32_t)b - lo, span) : 0u;
-    return da | (db << 16);
+// d' = clamp(d - lo, 0, span) on a pair of u16, for lo >= 0 (so d = 0 maps
+// to 0).
+__device__ __forceinline__ uint32_t to_window(uint32_t z, uint32_t lolo, uint32_t span2) {
+    return pk_min(pk_sub_sat(z, lolo), span2);
 }
 
 // Row of 6 packed pixels (grey | d' << 16): columns [x0-1, x0 .. x0+3, x0+4].
@@ -458,15 +489,18 @@ struct Row6 {
     uint32_t p[6];
 };
 
-__device__ __forceinline__ Row6 make_row(const RawRow &raw, int32_t lo, uint32_t lolo,
-                                         uint32_t span2) {
-    const uint32_t D0 = to_window(raw.Z0, lo, lolo, span2);
-    const uint32_t D1 = to_window(raw.Z1, lo, lolo, span2);
+// s8 = 8 s and s16 = 16 s for the column shift s of load_row.
+__device__ __forceinline__ Row6 make_row(const RawRow &raw, uint32_t lolo, uint32_t span2,
+                                         uint32_t s8, uint32_t s16) {
+    const uint32_t G = raw.G >> s8;
+    const uint64_t Z = ((((uint64_t)raw.Z1) << 32) | raw.Z0) >> s16;
+    const uint32_t D0 = to_window((uint32_t)Z, lolo, span2);
+    const uint32_t D1 = to_window((uint32_t)(Z >> 32), lolo, span2);
     Row6 r;
-    r.p[1] = __builtin_amdgcn_perm(raw.G, D0, 0x01000C04u);
-    r.p[2] = __builtin_amdgcn_perm(raw.G, D0, 0x03020C05u);
-    r.p[3] = __builtin_amdgcn_perm(raw.G, D1, 0x01000C06u);
-    r.p[4] = __builtin_amdgcn_perm(raw.G, D1, 0x03020C07u);
+    r.p[1] = __builtin_amdgcn_perm(G, D0, 0x01000C04u);
+    r.p[2] = __builtin_amdgcn_perm(G, D0, 0x03020C05u);
+    r.p[3] = __builtin_amdgcn_perm(G, D1, 0x01000C06u);
+    r.p[4] = __builtin_amdgcn_perm(G, D1, 0x03020C07u);
     // Left halo = previous lane's last pixel, right halo = next lane's first.
     r.p[0] = __builtin_amdgcn_update_dpp(0u, r.p[4], 0x138, 0xF, 0xF, false);  // wave_shr:1
     r.p[5] = __builtin_amdgcn_update_dpp(0u, r.p[1], 0x130, 0xF, 0xF, false);  // wave_shl:1
@@ -497,14 +531,15 @@ __device__ __forceinline__ uint32_t compare_bits(const Row6 &A, const Row6 &B, c
     return acc;
 }
 
-// LDS of the fast path; 38.7 KB, so four workgroups fit a CU.
+// LDS of the fast path, about 23 KB: six workgroups fit a CU's LDS.
 struct FastShared {
-    // fp.dim = 2 * cells * 59 counters, then 64 per-lane discard slots.
-    __attribute__((aligned(16))) uint32_t hist[2 * 64 * kU59 + 64];
+    // cells * 59 words: the grey count of (cell, bin) in the low half, the
+    // depth count in the high half (a cell holds fewer than 65536 pixels).
+    __attribute__((aligned(16))) uint32_t hist[64 * kU59];
     MedianScratch ms;
     uint8_t bin[256];    // code -> bin
-    uint8_t lut_g[256];  // grey comparison byte -> bin
-    uint8_t lut_d[256];  // depth comparison byte -> bin
+    uint8_t lut_g[256];  // grey comparison byte -> 4 x bin
+    uint8_t lut_d[256];  // depth comparison byte -> 4 x bin
     uint8_t rowband[LBPF_MAX_SIDE];
     uint8_t colband[LBPF_MAX_SIDE];
     float q[kQuot];
@@ -515,8 +550,59 @@ struct FastShared {
 __device__ __forceinline__ void load_tables(FastShared &sh, const uint8_t *tables) {
     for (int i = threadIdx.x; i < 256; i += kThreads) {
         sh.bin[i] = tables[i];
-        sh.lut_g[i] = tables[256 + i];
-        sh.lut_d[i] = tables[512 + i];
+        sh.lut_g[i] = (uint8_t)(4 * tables[256 + i]);  // bins <= 58: byte offsets fit
+        sh.lut_d[i] = (uint8_t)(4 * tables[512 + i]);
+    }
+}
+
+// Normalisation and output of one crop by a block of kNT threads, after the
+// counting (the caller's barrier): n_in = total of the grey counts, T = 2 n_in,
+// grey count / T to out[0 .. half), depth count / T to out[half .. 2 half),
+// raw counts to cout when it is not null. maxc bounds every count, so when it
+// is below kQuot the quotients are tabulated once in q. red holds kNT / 64
+// words.
+template <int kNT>
+__device__ __forceinline__ void finish_crop(const uint32_t *hist, int half, int maxc, float *q,
+                                            uint32_t *red, float *out, uint32_t *cout) {
+    constexpr int kNW = kNT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t part = 0;
+    for (int i = tid; i < half; i += kNT) part += hist[i] & 0xFFFFu;
+    part = wave_sum(part);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    uint32_t n_in = 0;
+#pragma unroll
+    for (int i = 0; i < kNW; ++i) n_in += red[i];
+    const float T = (float)(2u * n_in);
+    const bool tab = maxc < kQuot;
+    if (tab) {
+        for (int v = tid; v <= maxc; v += kNT) q[v] = n_in ? (float)v / T : 0.0f;
+        __syncthreads();
+    }
+    const bool vec = (half & 3) == 0 && ((uintptr_t)out & 15) == 0 && ((uintptr_t)cout & 15) == 0;
+    if (vec && tab) {
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        for (int i = 4 * tid; i < half; i += 4 * kNT) {
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(&hist[i]);
+            const u32x4 g = v & 0xFFFFu, d = v >> 16;
+            st_nt(reinterpret_cast<f32x4 *>(out + i), f32x4{q[g.x], q[g.y], q[g.z], q[g.w]});
+            st_nt(reinterpret_cast<f32x4 *>(out + half + i), f32x4{q[d.x], q[d.y], q[d.z], q[d.w]});
+            if (cout) {
+                *reinterpret_cast<u32x4 *>(cout + i) = g;
+                *reinterpret_cast<u32x4 *>(cout + half + i) = d;
+            }
+        }
+    } else {
+        for (int i = tid; i < half; i += kNT) {
+            const uint32_t v = hist[i], g = v & 0xFFFFu, d = v >> 16;
+            out[i] = tab ? q[g] : (n_in ? (float)g / T : 0.0f);
+            out[half + i] = tab ? q[d] : (n_in ? (float)d / T : 0.0f);
+            if (cout) {
+                cout[i] = g;
+                cout[half + i] = d;
+            }
+        }
     }
 }
 
@@ -524,14 +610,19 @@ __device__ __forceinline__ void load_tables(FastShared &sh, const uint8_t *table
 // not null) of length fp.dim. The tables must already be in LDS; the caller
 // separates consecutive crops with a barrier. kPF = rows loaded ahead.
 template <int kPF, bool kEarly>
-__device__ void fast_crop(const CropDesc &c, const FeatParams &fp, FastShared &sh, float *out,
+__device__ void fast_crop(const CropDesc &cd, const FeatParams &fp, FastShared &sh, float *out,
                           uint32_t *cout) {
+    // A private copy: the descriptor then lives in registers and is not
+    // re-read after every LDS atomic that might alias it.
+    const CropDesc c = cd;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int w = c.w, h = c.h;
     const int gx = fp.grid_x, gy = fp.grid_y, cells = gx * gy;
-    const int dim = fp.dim;
 
-    for (int i = tid; i < dim + 64; i += kThreads) sh.hist[i] = 0;
+    const int half = cells * kU59;  // words of sh.hist; half of dim
+    // 64 * 59 is a multiple of 4, so the rounded-up clear stays in the array.
+    for (int i = 4 * tid; i < half; i += 4 * kThreads)
+        *reinterpret_cast<u32x4 *>(&sh.hist[i]) = u32x4{0u, 0u, 0u, 0u};
     // Coordinate y lies in band floor(((y + 1) g - 1) / n) of a side of length n.
     for (int y = tid; y < h; y += kThreads) sh.rowband[y] = (uint8_t)(((y + 1) * gy - 1) / h);
     for (int x = tid; x < w; x += kThreads) sh.colband[x] = (uint8_t)(((x + 1) * gx - 1) / w);
@@ -539,7 +630,8 @@ __device__ void fast_crop(const CropDesc &c, const FeatParams &fp, FastShared &s
     // Stream geometry of the code phase. Its first rows do not depend on the
     // median: with kEarly their loads are issued now and land while the
     // median is computed (at the price of registers held across it).
-    const bool fast = w <= kFastMaxW;
+    // The lane loads need w >= 4 unless the crop may be over-read.
+    const bool fast = w <= kFastMaxW && (w >= 4 || (c.flags & kCropOverReadOk));
     const int L = (w + 3) >> 2;           // lanes per stream (<= 64 when fast)
     const int spw = fast ? 64 / L : 1;    // streams per wave
     const int sw = lane / L;              // stream of this lane within the wave
@@ -547,30 +639,44 @@ __device__ void fast_crop(const CropDesc &c, const FeatParams &fp, FastShared &s
     const int S = kWaves * spw;
     const int s = wave * spw + (sw < spw ? sw : 0);
     const int rows = h - 2;
+    // Stream s owns rows yb .. yb + n_own - 1. Every lane of the block steps
+    // through n_step >= n_own rows, so the row loop is uniform; the rows past
+    // a lane's own are loaded and coded but not counted. They stay inside the
+    // crop: floor(s R / S) + ceil(R / S) <= R, so the last centre row
+    // yb + n_step - 1 <= h - 2 and its lower neighbour row <= h - 1.
     const int yb = 1 + (s * rows) / S;
-    const int ye = (fast && sw < spw) ? 1 + ((s + 1) * rows) / S : yb;
+    const int n_own = (fast && sw < spw) ? 1 + ((s + 1) * rows) / S - yb : 0;
+    const int n_step = (rows + S - 1) / S;
     const bool full = (c.flags & kCropOverReadOk) || x0 + 4 <= w;
+    const int xl = full ? x0 : w - 4;
+    const uint32_t s8 = 8u * (uint32_t)(x0 - xl), s16 = 2u * s8;
     RawRow rawA, rawB, ring[kPF];
     auto prime = [&]() {
-        rawA = load_row(c, yb - 1, x0, full);
-        rawB = load_row(c, yb, x0, full);
+        rawA = load_row(c, yb - 1, xl);
+        rawB = load_row(c, yb, xl);
 #pragma unroll
-        for (int u = 0; u < kPF; ++u) ring[u] = load_row(c, min(yb + 1 + u, h - 1), x0, full);
+        for (int u = 0; u < kPF; ++u) ring[u] = load_row(c, min(yb + 1 + u, h - 1), xl);
     };
-    if (kEarly && yb < ye) prime();
+    if (kEarly && fast) prime();
 
-    const int32_t m = crop_median_fast(c, sh.ms, sh.red);  // ends with a barrier
-
-    if (fast) {
-        if (m >= 0 && yb < ye) {
+    // Ends with a barrier; the same value in every lane.
+    const int32_t m = __builtin_amdgcn_readfirstlane(crop_median_fast(c, sh.ms, sh.red));
+    const int32_t lo = m - fp.window;
+    // The packed window arithmetic needs lo >= 0: a crop whose median lies
+    // within the window of 0 takes the generic path.
+    if (fast && (m < 0 || lo >= 0)) {
+        if (m >= 0) {
             if (!kEarly) prime();
-            const int32_t lo = m - fp.window;
-            const uint32_t lolo = (uint32_t)(lo & 0xFFFF) * 0x10001u;
+            const uint32_t lolo = (uint32_t)lo * 0x10001u;
             const uint32_t span2 = (uint32_t)(2 * fp.window) * 0x10001u;
             const uint32_t in_hi = (uint32_t)(2 * fp.window - 1) << 16;
 
             // Per column: histogram column offset (bytes) and in-window
             // threshold (0 for border or out-of-crop columns: never counted).
+            // A pixel counts when its packed word plus the row's bias is
+            // below the threshold: the bias subtracts 1 from d' in rows the
+            // lane owns (so 1 <= d' < 2 window passes) and lifts d' above
+            // every threshold in the others.
             uint32_t col4[4], thr[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -578,72 +684,56 @@ __device__ void fast_crop(const CropDesc &c, const FeatParams &fp, FastShared &s
                 col4[k] = (uint32_t)(sh.colband[min(x, w - 1)] * kU59) * 4u;
                 thr[k] = (x >= 1 && x <= w - 2) ? in_hi : 0u;
             }
-            const uint32_t dep4 = (uint32_t)(cells * kU59) * 4u;
             char *hbase = reinterpret_cast<char *>(sh.hist);
 
-            Row6 A = make_row(rawA, lo, lolo, span2);
-            Row6 B = make_row(rawB, lo, lolo, span2);
-            for (int y = yb; y < ye; y += kPF) {
+            Row6 A = make_row(rawA, lolo, span2, s8, s16);
+            Row6 B = make_row(rawB, lolo, span2, s8, s16);
+            // One row: code the centre row B against A and C = the row in
+            // `slot`, count it, then refill `slot` kPF rows ahead.
+            auto step = [&](const int tt, RawRow &slot, const bool refill) {
+                const int yy = yb + tt;
+                const Row6 C = make_row(slot, lolo, span2, s8, s16);
+                if (refill) slot = load_row(c, min(yy + 1 + kPF, h - 1), xl);
+                const uint32_t bias = tt < n_own ? 0xFFFF0000u : 0x7FFF0000u;
+                const uint32_t row4 = (uint32_t)(sh.rowband[yy] * gx * kU59) * 4u;
 #pragma unroll
-                for (int u = 0; u < kPF; ++u) {
-                    const int yy = y + u;
-                    if (yy >= ye) break;
-                    const Row6 C = make_row(ring[u], lo, lolo, span2);
-                    ring[u] = load_row(c, min(yy + 1 + kPF, h - 1), x0, full);
-                    const uint32_t row4 = (uint32_t)(sh.rowband[yy] * gx * kU59) * 4u;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const uint32_t bits = compare_bits(A, B, C, k + 1);
-                        if (B.p[k + 1] - 0x10000u < thr[k]) {
-                            const uint32_t base = row4 + col4[k];
-                            const uint32_t bg = sh.lut_g[(bits >> 8) & 0xFFu];
-                            const uint32_t bd = sh.lut_d[bits >> 24];
-                            atomicAdd(reinterpret_cast<uint32_t *>(hbase + base + 4u * bg), 1u);
-                            atomicAdd(reinterpret_cast<uint32_t *>(hbase + dep4 + base + 4u * bd), 1u);
-                        }
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t bits = compare_bits(A, B, C, k + 1);
+                    if (B.p[k + 1] + bias < thr[k]) {
+                        // The tables hold 4 x bin: byte offsets.
+                        const uint32_t og = sh.lut_g[(bits >> 8) & 0xFFu];
+                        const uint32_t od = sh.lut_d[bits >> 24];
+                        atomicAdd(reinterpret_cast<uint32_t *>(hbase + (row4 + col4[k] + og)), 1u);
+                        atomicAdd(reinterpret_cast<uint32_t *>(hbase + (row4 + col4[k] + od)),
+                                  0x10000u);
                     }
-                    A = B;
-                    B = C;
                 }
+                A = B;
+                B = C;
+            };
+            // Whole groups of kPF rows whose refills are all needed, in a
+            // loop with no other exit, so the wait for each ring slot counts
+            // exactly the loads issued after it; then the last rows, which
+            // refill only rows that are still to be coded (row tt's refill
+            // is row tt + 1 + kPF, needed while that is <= n_step).
+            int t = 0;
+            for (; t + kPF <= n_step; t += kPF) {
+#pragma unroll
+                for (int u = 0; u < kPF; ++u) step(t + u, ring[u], true);
+            }
+#pragma unroll
+            for (int u = 0; u < kPF - 1; ++u) {
+                if (t + u >= n_step) break;  // uniform
+                step(t + u, ring[u], false);
             }
         }
     } else {
-        lbp_hist_generic(c, fp, m, sh.bin, sh.rowband, sh.colband, sh.hist);
+        lbp_hist_generic(c, fp, m, sh.bin, sh.rowband, sh.colband, sh.hist, true);
     }
     __syncthreads();
 
-    // n_in = total of the grey half; T = 2 n_in.
-    uint32_t part = 0;
-    for (int i = tid; i < cells * kU59; i += kThreads) part += sh.hist[i];
-    part = wave_sum(part);
-    if (lane == 0) sh.red[wave] = part;
-    __syncthreads();
-    uint32_t n_in = 0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) n_in += sh.red[i];
-    const float T = (float)(2u * n_in);
-    const int maxc = ((h + gy - 1) / gy) * ((w + gx - 1) / gx);  // cell capacity bound
-    const bool tab = maxc < kQuot;
-    if (tab) {
-        for (int v = tid; v <= maxc; v += kThreads) sh.q[v] = n_in ? (float)v / T : 0.0f;
-        __syncthreads();
-    }
-    const bool vec = (dim & 3) == 0 && ((uintptr_t)out & 15) == 0 && ((uintptr_t)cout & 15) == 0;
-    if (vec && tab) {
-        typedef float f32x4 __attribute__((ext_vector_type(4)));
-        for (int i = 4 * tid; i < dim; i += 4 * kThreads) {
-            const u32x4 v = *reinterpret_cast<const u32x4 *>(&sh.hist[i]);
-            const f32x4 f = {sh.q[v.x], sh.q[v.y], sh.q[v.z], sh.q[v.w]};
-            *reinterpret_cast<f32x4 *>(out + i) = f;
-            if (cout) *reinterpret_cast<u32x4 *>(cout + i) = v;
-        }
-    } else {
-        for (int i = tid; i < dim; i += kThreads) {
-            const uint32_t v = sh.hist[i];
-            out[i] = tab ? sh.q[v] : (n_in ? (float)v / T : 0.0f);
-            if (cout) cout[i] = v;
-        }
-    }
+    finish_crop<kThreads>(sh.hist, half, ((h + gy - 1) / gy) * ((w + gx - 1) / gx), sh.q, sh.red,
+                          out, cout);
 }
 
 // One workgroup per crop.
@@ -674,8 +764,10 @@ __global__ __launch_bounds__(kThreads) void k_features_persistent(
     for (;;) {
         if (threadIdx.x == 0) sh.next = (int32_t)atomicAdd(&queue[0], 1u);
         __syncthreads();
-        const int32_t j = sh.next;
-        if (j >= n) break;  // uniform: every thread read the same j
+        // Every thread read the same j; readfirstlane tells the compiler so,
+        // and the crop's descriptor is then fetched with scalar loads.
+        const int32_t j = __builtin_amdgcn_readfirstlane(sh.next);
+        if (j >= n) break;
         const size_t i = order ? (size_t)order[j] : (size_t)j;
         fast_crop<kPF, false>(crops[i], fp, sh, hist + i * fp.dim, counts ? counts + i * fp.dim : nullptr);
         __syncthreads();
@@ -758,8 +850,11 @@ __global__ __launch_bounds__(kThreads) void k_debug_codes(const CropDesc *__rest
 }  // namespace
 
 bool fast_path_ok(const FeatParams &fp) {
+    // Packed 16-bit counters: a cell of the largest crop holds < 65536 pixels.
+    const int64_t cell_max = (int64_t)((LBPF_MAX_SIDE + fp.grid_x - 1) / fp.grid_x) *
+                             ((LBPF_MAX_SIDE + fp.grid_y - 1) / fp.grid_y);
     return fp.nbins == kU59 && fp.use_grey && fp.use_depth && fp.window >= 1 &&
-           fp.window <= 255 && fp.grid_x * fp.grid_y <= 64;
+           fp.window <= 255 && fp.grid_x * fp.grid_y <= 64 && cell_max < 65536;
 }
 
 hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &fp,

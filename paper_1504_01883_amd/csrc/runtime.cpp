@@ -388,7 +388,7 @@ lbpf_status lbpf_tune_batch(lbpf_ctx *ctx, lbpf_batch *batch, float *hist, int32
     hipStream_t s = (hipStream_t)stream;
     std::vector<lbpf_launch_cfg> cands;
     for (int pf : {2, 4, 8}) cands.push_back({0, 4, pf, 1});
-    for (int m : {2, 3, 4})
+    for (int m : {2, 4, 5, 6})
         for (int pf : {2, 4})
             for (int so : {0, 1}) cands.push_back({1, m, pf, so});
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -110,6 +110,53 @@ def test_degenerate_crops(ctx, ref):
     assert n_in[0] == 0 and not hist[0].any()
 
 
+def _staged_trap(w, h):
+    """Depth 2000 everywhere but 1000 at the 64 points the median estimate
+    samples (8 x 8 grid): the estimate misses the median by 1000 mm, so the
+    exact select runs instead of the window lookup."""
+    g, z = synth.render_crop(w, h, synth.W_TINY, 4, 3100)
+    z = np.full((h, w), 2000, np.uint16)
+    for i in range(8):
+        for j in range(8):
+            z[((2 * i + 1) * h) >> 4, ((2 * j + 1) * w) >> 4] = 1000
+    return g, z
+
+
+def test_aligned_crops_bitexact(ctx, ref):
+    """Crops whose widths are multiples of 16 with 16-byte aligned rows, up to
+    16384 pixels (1 to 64 lanes per row stream, up to 1024 rows): no valid
+    depth, a median below the window (generic counting), a median the estimate
+    misses (exact select), a saturated depth plane, and boxes read in place
+    from a frame."""
+    crops = [synth.render_crop(w, h, synth.W_TINY, i % 5, 3000 + i) for i, (w, h) in
+             enumerate([(16, 3), (16, 1024), (256, 64), (48, 37), (128, 128), (240, 68),
+                        (32, 5), (64, 64)])]
+    crops.append((np.full((20, 32), 7, np.uint8), np.zeros((20, 32), np.uint16)))
+    g, z = synth.render_crop(64, 16, synth.W_TINY, 1, 3050)
+    crops.append((g, (z % 97 + 20).astype(np.uint16)))  # median < 150: lo < 0
+    crops.append(_staged_trap(64, 64))
+    crops.append((np.full((16, 16), 200, np.uint8), np.full((16, 16), 65535, np.uint16)))
+    planes = [lbpf.to_device_planes(g, z) for g, z in crops]
+    boxes = [[i, 0, 0, z.shape[1], z.shape[0]] for i, (g, z) in enumerate(crops)]
+    hist, cnt = ctx.features(planes, boxes, with_counts=True)
+    torch.cuda.synchronize()
+    f, c, n_in = ref.features(crops, boxes, n_threads=8)
+    _assert_bitexact(hist.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), f, c)
+    assert n_in[8] == 0 and not hist[8].any()
+
+    rng = np.random.default_rng(7)
+    H, W = 480, 640
+    G = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    Z = rng.integers(500, 1500, size=(H, W)).astype(np.uint16)
+    Z[rng.random((H, W)) < 0.05] = 0
+    fb = [[0, 32, 48, 128, 128], [0, 496, 400, 144, 80], [0, 0, 0, 16, 480], [0, 624, 0, 16, 3]]
+    dg, dz = lbpf.to_device_planes(G, Z)
+    hist, cnt = ctx.features([(dg, dz)], fb, with_counts=True)
+    torch.cuda.synchronize()
+    f, c, _ = ref.features([(G, Z)], fb, n_threads=8)
+    _assert_bitexact(hist.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), f, c)
+
+
 @pytest.mark.parametrize("grid,mapping,window,modality", [
     ((8, 8), lbpf.MAP_U59, 0, lbpf.MOD_BOTH),
     ((8, 8), lbpf.MAP_U59, 150, lbpf.MOD_GREY),
