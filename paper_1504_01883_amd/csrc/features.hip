@@ -291,6 +291,14 @@ __device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t m, uint32_t c) {
     return r;
 }
 
+// a + b + c in one instruction; written out because the compiler otherwise
+// shares a + b between two such sums and spends three adds on them.
+__device__ __forceinline__ uint32_t add3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
                                                                   __builtin_bit_cast(u16x2, b)));
@@ -502,8 +510,10 @@ __device__ __forceinline__ Row6 make_row(const RawRow &raw, uint32_t lolo, uint3
     r.p[3] = __builtin_amdgcn_perm(G, D1, 0x01000C06u);
     r.p[4] = __builtin_amdgcn_perm(G, D1, 0x03020C07u);
     // Left halo = previous lane's last pixel, right halo = next lane's first.
-    r.p[0] = __builtin_amdgcn_update_dpp(0u, r.p[4], 0x138, 0xF, 0xF, false);  // wave_shr:1
-    r.p[5] = __builtin_amdgcn_update_dpp(0u, r.p[1], 0x130, 0xF, 0xF, false);  // wave_shl:1
+    // bound_ctrl: the lane with no source (0, resp. 63) reads 0, and no old
+    // value has to be set up first.
+    r.p[0] = __builtin_amdgcn_mov_dpp(r.p[4], 0x138, 0xF, 0xF, true);  // wave_shr:1
+    r.p[5] = __builtin_amdgcn_mov_dpp(r.p[1], 0x130, 0xF, 0xF, true);  // wave_shl:1
     return r;
 }
 
@@ -703,19 +713,17 @@ __device__ void fast_crop(const CropDesc &cd, const FeatParams &fp, FastShared &
                         // The tables hold 4 x bin: byte offsets.
                         const uint32_t og = sh.lut_g[(bits >> 8) & 0xFFu];
                         const uint32_t od = sh.lut_d[bits >> 24];
-                        atomicAdd(reinterpret_cast<uint32_t *>(hbase + (row4 + col4[k] + og)), 1u);
-                        atomicAdd(reinterpret_cast<uint32_t *>(hbase + (row4 + col4[k] + od)),
+                        atomicAdd(reinterpret_cast<uint32_t *>(hbase + add3(row4, col4[k], og)), 1u);
+                        atomicAdd(reinterpret_cast<uint32_t *>(hbase + add3(row4, col4[k], od)),
                                   0x10000u);
                     }
                 }
                 A = B;
                 B = C;
             };
-            // Whole groups of kPF rows whose refills are all needed, in a
-            // loop with no other exit, so the wait for each ring slot counts
-            // exactly the loads issued after it; then the last rows, which
-            // refill only rows that are still to be coded (row tt's refill
-            // is row tt + 1 + kPF, needed while that is <= n_step).
+            // Whole groups of kPF rows in a loop with no other exit, so the
+            // wait for each ring slot counts exactly the loads issued after
+            // it; then the remaining rows, which need no refill.
             int t = 0;
             for (; t + kPF <= n_step; t += kPF) {
 #pragma unroll
