@@ -769,15 +769,21 @@ __global__ __launch_bounds__(kThreads) void k_features_persistent(
     uint32_t *__restrict__ counts, uint32_t *__restrict__ queue) {
     __shared__ FastShared sh;
     load_tables(sh, tables);
+    if (threadIdx.x == 0) sh.next = (int32_t)atomicAdd(&queue[0], 1u);
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) sh.next = (int32_t)atomicAdd(&queue[0], 1u);
-        __syncthreads();
         // Every thread read the same j; readfirstlane tells the compiler so,
         // and the crop's descriptor is then fetched with scalar loads.
         const int32_t j = __builtin_amdgcn_readfirstlane(sh.next);
         if (j >= n) break;
+        // The next position is taken now and published after this crop, so
+        // the atomic's latency overlaps the crop (a workgroup takes one
+        // position past the end on its way out).
+        uint32_t next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(&queue[0], 1u);
         const size_t i = order ? (size_t)order[j] : (size_t)j;
         fast_crop<kPF, false>(crops[i], fp, sh, hist + i * fp.dim, counts ? counts + i * fp.dim : nullptr);
+        if (threadIdx.x == 0) sh.next = (int32_t)next;
         __syncthreads();
     }
     if (threadIdx.x == 0) {
