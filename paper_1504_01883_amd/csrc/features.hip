@@ -2,33 +2,36 @@
 //
 // One workgroup (4 wave64) per face crop; every step runs inside one launch:
 //   1. exact lower median m of the crop's non-zero depth (the depth region of
-//      interest of the paper's fusion), by a two-level radix select: a 256-bin
-//      histogram of the high bytes, then of the low bytes inside the selected
-//      high byte;
+//      interest of the paper's fusion);
 //   2. for every interior pixel whose depth d satisfies d != 0 and
 //      |d - m| < window, the 3x3 LBP code of the grey and of the depth plane
 //      (Sec. 2.4, Eq. 2: neighbour p has weight 2^p and its bit is set when it
 //      is >= the centre; p0 = top-left neighbour, then clockwise);
 //   3. code -> uniform-59 bin through a 256-entry LDS table;
-//   4. increments of the [channel][ry][rx][bin] regional histogram (Eq. 3)
-//      held in LDS;
+//   4. increments of the regional histograms (Eq. 3) held in LDS;
 //   5. the row written once to HBM as count / T, T = channels * n_in, each
 //      quotient the correctly rounded IEEE single division (and optionally the
 //      raw counts).
 //
-// Two kernels:
-//   k_features_fast  -- the default configuration (uniform-59 bins, both
-//                       channels, window 1..255 mm). Crops up to 256 px wide
-//                       take the fast path below; wider crops fall back to the
-//                       generic per-pixel loop inside the same launch.
-//   k_features_generic -- every other configuration (256 bins, one channel,
-//                       mask off, wide windows).
+// Kernels:
+//   k_features_fast       -- the default configuration (uniform-59 bins, both
+//                            channels, window 1..255 mm), one workgroup per
+//                            crop. Crops up to 256 px wide take the lane path
+//                            below; wider crops (and crops whose median lies
+//                            within the window of 0) the per-pixel loop,
+//                            inside the same launch.
+//   k_features_persistent -- the same per crop, a fixed grid taking crops
+//                            from a self-resetting work queue (ragged batches).
+//   k_features_generic    -- every other configuration (256 bins, one
+//                            channel, mask off, wide windows).
 //
-// Fast path, per crop:
-//   * Median: each thread loads 8 depth pixels per 16-byte load and adds them
-//     to the high-byte histogram as one count for the pixels sharing the
-//     first pixel's high byte (smooth depth makes that the common case) plus
-//     one count per other pixel, so contention on the LDS atomics stays low.
+// Default configuration, per crop:
+//   * Median: wave 0 estimates it from 64 pixels on an 8 x 8 grid; one pass
+//     over the crop then histograms the 256 mm window around the estimate
+//     (1 mm bins, LDS atomics on well-spread addresses) and counts non-zero
+//     pixels and pixels above the window's start in packed 16-bit registers;
+//     when the median falls in the window the histogram gives it, otherwise
+//     an exact two-level radix select (high byte, then low byte) runs.
 //   * Codes: lanes own 4 adjacent columns and walk down a band of rows with a
 //     3-row register window. Each pixel is packed as (grey | d' << 16) with
 //     d' = clamp(d - (m - window), 0, 2 window) (0 for d = 0): clamping keeps
@@ -39,6 +42,8 @@
 //     one AND-OR per neighbour deposits the grey bit and the depth bit into
 //     distinct positions of one accumulator. Halo columns come from the
 //     neighbouring lanes through DPP wave shifts.
+//   * Counters: one LDS word per (cell, bin), the grey count in its low 16
+//     bits and the depth count in its high 16 bits.
 //   * Normalisation: count / T is tabulated once per crop for every count a
 //     cell can hold, then the row is written by table lookup.
 #include "lbpf_internal.h"
