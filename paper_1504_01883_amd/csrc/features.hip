@@ -37,11 +37,11 @@
 //     d' = clamp(d - (m - window), 0, 2 window) (0 for d = 0): clamping keeps
 //     every comparison against an in-window centre unchanged and makes the
 //     depth fit 9 bits, so ONE packed 16-bit subtraction per neighbour yields
-//     both channels' comparisons. For a negative difference the high bits of
-//     each 16-bit half are all ones (bits 8..15 for grey, 9..15 for d'), so
-//     one AND-OR per neighbour deposits the grey bit and the depth bit into
-//     distinct positions of one accumulator. Halo columns come from the
-//     neighbouring lanes through DPP wave shifts.
+//     both channels' comparisons: the sign bit of each 16-bit half. Byte
+//     permutes gather the sign bits of two neighbours per instruction and
+//     masked AND-ORs merge them into one word holding both channels'
+//     comparison bytes. Halo columns come from the neighbouring lanes through
+//     DPP wave shifts.
 //   * Counters: one LDS word per (cell, bin), the grey count in its low 16
 //     bits and the depth count in its high 16 bits.
 //   * Normalisation: count / T is tabulated once per crop for every count a
@@ -491,6 +491,17 @@ __device__ __forceinline__ RawRow load_row(const CropDesc &c, int y, int xl) {
     return r;
 }
 
+// load_row at byte offsets goff (grey plane) and doff (depth plane) from the
+// crop's origin.
+__device__ __forceinline__ RawRow load_row_at(const CropDesc &c, uint32_t goff, uint32_t doff) {
+    RawRow r;
+    r.G = gld<uint32_t>(c.grey, goff);
+    const u32x2 z = gld<u32x2>(c.depth, doff);
+    r.Z0 = z.x;
+    r.Z1 = z.y;
+    return r;
+}
+
 // d' = clamp(d - lo, 0, span) on a pair of u16, for lo >= 0 (so d = 0 maps
 // to 0).
 __device__ __forceinline__ uint32_t to_window(uint32_t z, uint32_t lolo, uint32_t span2) {
@@ -522,11 +533,31 @@ __device__ __forceinline__ Row6 make_row(const RawRow &raw, uint32_t lolo, uint3
     return r;
 }
 
+// Byte 0 | byte 1 and byte 2 | byte 3 of x, one SDWA instruction each.
+__device__ __forceinline__ uint32_t or_b01(uint32_t x) {
+    uint32_t r;
+    asm("v_or_b32_sdwa %0, %1, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_1"
+        : "=v"(r)
+        : "v"(x));
+    return r;
+}
+__device__ __forceinline__ uint32_t or_b23(uint32_t x) {
+    uint32_t r;
+    asm("v_or_b32_sdwa %0, %1, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_2 src1_sel:BYTE_3"
+        : "=v"(r)
+        : "v"(x));
+    return r;
+}
+
 // Comparison bits of the centre B[j] against its 8 neighbours in rows A
-// (y-1), B (y), C (y+1): grey bit of neighbour p at 8+p, depth bit of
-// neighbour p at 25+p (p < 7) and of p7 at 24. A set bit means the
-// neighbour is BELOW the centre. For a negative 16-bit difference every bit
-// from 8 (grey, |diff| < 256) or 9 (depth, |diff| < 512) up is set.
+// (y-1), B (y), C (y+1). A set bit means the neighbour is BELOW the centre:
+// the sign of the packed 16-bit difference neighbour - centre, bit 15 for
+// grey and bit 31 for depth. v_perm's selectors 8-11 replicate those sign
+// bits into whole bytes, so each perm gathers the four signs of two
+// neighbours (bytes: grey of the first, grey of the second, depth of the
+// first, depth of the second); the masks then keep bit p for neighbour p.
+// Grey index = byte 0 | byte 1, depth index = byte 2 | byte 3 (or_b01,
+// or_b23): bit p <-> neighbour p in both.
 __device__ __forceinline__ uint32_t compare_bits(const Row6 &A, const Row6 &B, const Row6 &C, int j) {
     const uint32_t c = B.p[j];
     // All eight differences first: a packed result read by the very next
@@ -534,15 +565,12 @@ __device__ __forceinline__ uint32_t compare_bits(const Row6 &A, const Row6 &B, c
     const uint32_t d0 = pk_sub(A.p[j - 1], c), d1 = pk_sub(A.p[j], c), d2 = pk_sub(A.p[j + 1], c);
     const uint32_t d3 = pk_sub(B.p[j + 1], c), d4 = pk_sub(C.p[j + 1], c), d5 = pk_sub(C.p[j], c);
     const uint32_t d6 = pk_sub(C.p[j - 1], c), d7 = pk_sub(B.p[j - 1], c);
-    uint32_t acc = d0 & 0x02000100u;
-    acc = and_or(d1, 0x04000200u, acc);
-    acc = and_or(d2, 0x08000400u, acc);
-    acc = and_or(d3, 0x10000800u, acc);
-    acc = and_or(d4, 0x20001000u, acc);
-    acc = and_or(d5, 0x40002000u, acc);
-    acc = and_or(d6, 0x80004000u, acc);
-    acc = and_or(d7, 0x00008000u, acc);
-    acc = and_or(d7 >> 7, 0x01000000u, acc);
+    // perm(hi, lo, sel): 8 = sign of lo[15], 9 = lo[31], 10 = hi[15], 11 = hi[31].
+    constexpr uint32_t kSel = 0x090B080Au;
+    uint32_t acc = __builtin_amdgcn_perm(d0, d1, kSel) & 0x02010201u;
+    acc = and_or(__builtin_amdgcn_perm(d2, d3, kSel), 0x08040804u, acc);
+    acc = and_or(__builtin_amdgcn_perm(d4, d5, kSel), 0x20102010u, acc);
+    acc = and_or(__builtin_amdgcn_perm(d6, d7, kSel), 0x80408040u, acc);
     return acc;
 }
 
@@ -553,10 +581,10 @@ struct FastShared {
     __attribute__((aligned(16))) uint32_t hist[64 * kU59];
     MedianScratch ms;
     uint8_t bin[256];    // code -> bin
-    uint8_t lut_g[256];  // grey comparison byte -> 4 x bin
-    uint8_t lut_d[256];  // depth comparison byte -> 4 x bin
+    uint8_t lut[256];    // comparison byte (bit p: neighbour p below) -> 4 x bin
     uint8_t rowband[LBPF_MAX_SIDE];
     uint8_t colband[LBPF_MAX_SIDE];
+    uint16_t rowoff[LBPF_MAX_SIDE];  // byte offset of row y's band in hist
     float q[kQuot];
     uint32_t red[2 * kWaves];
     int32_t next;
@@ -565,8 +593,7 @@ struct FastShared {
 __device__ __forceinline__ void load_tables(FastShared &sh, const uint8_t *tables) {
     for (int i = threadIdx.x; i < 256; i += kThreads) {
         sh.bin[i] = tables[i];
-        sh.lut_g[i] = (uint8_t)(4 * tables[256 + i]);  // bins <= 58: byte offsets fit
-        sh.lut_d[i] = (uint8_t)(4 * tables[512 + i]);
+        sh.lut[i] = (uint8_t)(4 * tables[256 + i]);  // bins <= 58: byte offsets fit
     }
 }
 
@@ -639,7 +666,11 @@ __device__ void fast_crop(const CropDesc &cd, const FeatParams &fp, FastShared &
     for (int i = 4 * tid; i < half; i += 4 * kThreads)
         *reinterpret_cast<u32x4 *>(&sh.hist[i]) = u32x4{0u, 0u, 0u, 0u};
     // Coordinate y lies in band floor(((y + 1) g - 1) / n) of a side of length n.
-    for (int y = tid; y < h; y += kThreads) sh.rowband[y] = (uint8_t)(((y + 1) * gy - 1) / h);
+    for (int y = tid; y < h; y += kThreads) {
+        const int band = ((y + 1) * gy - 1) / h;
+        sh.rowband[y] = (uint8_t)band;
+        sh.rowoff[y] = (uint16_t)(band * gx * kU59 * 4);  // < 64 * 59 * 4
+    }
     for (int x = tid; x < w; x += kThreads) sh.colband[x] = (uint8_t)(((x + 1) * gx - 1) / w);
 
     // Stream geometry of the code phase. Its first rows do not depend on the
@@ -705,19 +736,28 @@ __device__ void fast_crop(const CropDesc &cd, const FeatParams &fp, FastShared &
             Row6 B = make_row(rawB, lolo, span2, s8, s16);
             // One row: code the centre row B against A and C = the row in
             // `slot`, count it, then refill `slot` kPF rows ahead.
+            // Byte offsets of the next row to refill, kept running so the loop
+            // has no multiplies; rows past h - 1 clamp to it (the offsets
+            // grow with the row).
+            const uint32_t gstep = (uint32_t)c.grey_pitch, dstep = 2u * (uint32_t)c.depth_pitch;
+            const uint32_t r0 = (uint32_t)(yb + 1 + kPF), rl = (uint32_t)(h - 1);
+            uint32_t gnext = r0 * gstep + (uint32_t)xl, dnext = r0 * dstep + 2u * (uint32_t)xl;
+            const uint32_t gmax = rl * gstep + (uint32_t)xl, dmax = rl * dstep + 2u * (uint32_t)xl;
             auto step = [&](const int tt, RawRow &slot, const bool refill) {
                 const int yy = yb + tt;
                 const Row6 C = make_row(slot, lolo, span2, s8, s16);
-                if (refill) slot = load_row(c, min(yy + 1 + kPF, h - 1), xl);
+                if (refill) slot = load_row_at(c, min(gnext, gmax), min(dnext, dmax));
+                gnext += gstep;
+                dnext += dstep;
                 const uint32_t bias = tt < n_own ? 0xFFFF0000u : 0x7FFF0000u;
-                const uint32_t row4 = (uint32_t)(sh.rowband[yy] * gx * kU59) * 4u;
+                const uint32_t row4 = sh.rowoff[yy];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const uint32_t bits = compare_bits(A, B, C, k + 1);
                     if (B.p[k + 1] + bias < thr[k]) {
-                        // The tables hold 4 x bin: byte offsets.
-                        const uint32_t og = sh.lut_g[(bits >> 8) & 0xFFu];
-                        const uint32_t od = sh.lut_d[bits >> 24];
+                        // The table holds 4 x bin: byte offsets.
+                        const uint32_t og = sh.lut[or_b01(bits)];
+                        const uint32_t od = sh.lut[or_b23(bits)];
                         atomicAdd(reinterpret_cast<uint32_t *>(hbase + add3(row4, col4[k], og)), 1u);
                         atomicAdd(reinterpret_cast<uint32_t *>(hbase + add3(row4, col4[k], od)),
                                   0x10000u);

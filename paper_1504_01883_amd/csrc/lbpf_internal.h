@@ -38,7 +38,7 @@ struct FeatParams {
 
 // Code -> bin tables, built on the host by construction (tables.cpp).
 void build_uniform59(uint8_t out[256]);
-void build_comparison_luts(const uint8_t bin[256], uint8_t grey[256], uint8_t depth[256]);
+void build_comparison_lut(const uint8_t bin[256], uint8_t below[256]);
 bool fast_path_ok(const FeatParams &fp);
 
 // Launch shape of the fast feature kernel (chosen per batch by the tuner).

@@ -204,20 +204,20 @@ lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_
     if (e != hipSuccess) return cleanup(fail_hip(e, "hipDeviceGetAttribute"));
 
     const size_t stage_bytes = sizeof(CropDesc) * LBPF_MAX_BOXES_PER_CALL;
-    const size_t ws = 768 + kRing * stage_bytes + kScoreScratchElems * sizeof(float) +
+    const size_t ws = 512 + kRing * stage_bytes + kScoreScratchElems * sizeof(float) +
                       sizeof(int32_t) + sizeof(uint32_t) * (size_t)fp.dim +
                       kPartElems * sizeof(float);
     if (!charge(ctx, ws)) return cleanup(fail(LBPF_E_BUDGET, "workspace exceeds the HBM budget"));
 
-    // Tables: [0,256) code -> bin; [256,512) grey comparison byte -> bin;
-    // [512,768) depth comparison byte -> bin (layouts in features.hip).
-    uint8_t table[768];
+    // Tables: [0,256) code -> bin; [256,512) comparison byte -> bin (the
+    // byte's layout is in features.hip).
+    uint8_t table[512];
     if (c.mapping == LBPF_MAP_U59) {
         build_uniform59(table);
     } else {
         for (int i = 0; i < 256; ++i) table[i] = (uint8_t)i;
     }
-    build_comparison_luts(table, table + 256, table + 512);
+    build_comparison_lut(table, table + 256);
     if ((e = hipMalloc(&ctx->d_bins, sizeof table)) != hipSuccess)
         return cleanup(fail_hip(e, "hipMalloc"));
     if ((e = hipMemcpy(ctx->d_bins, table, sizeof table, hipMemcpyHostToDevice)) != hipSuccess)

@@ -19,18 +19,11 @@ void build_uniform59(uint8_t out[256]) {
     for (int c = 0; c < 256; ++c) out[c] = uniform[c] ? (uint8_t)rank++ : (uint8_t)58;
 }
 
-// The fast feature kernel produces, per pixel, one byte per channel whose bit
-// is set when a neighbour is BELOW the centre (the complement of the LBP bit):
-//   grey byte:  bit p <-> neighbour p;
-//   depth byte: bit 0 <-> neighbour 7, bit p+1 <-> neighbour p (p < 7).
-// These tables map such a byte straight to the histogram bin.
-void build_comparison_luts(const uint8_t bin[256], uint8_t grey[256], uint8_t depth[256]) {
-    for (int i = 0; i < 256; ++i) {
-        const unsigned below_g = (unsigned)i;
-        const unsigned below_d = (((unsigned)i >> 1) | ((unsigned)i << 7)) & 0xFFu;
-        grey[i] = bin[~below_g & 0xFFu];
-        depth[i] = bin[~below_d & 0xFFu];
-    }
+// The fast feature kernel produces, per pixel and channel, a byte whose bit p
+// is set when neighbour p is BELOW the centre (the complement of the LBP bit
+// of Eq. 2). This table maps such a byte straight to the histogram bin.
+void build_comparison_lut(const uint8_t bin[256], uint8_t below[256]) {
+    for (int i = 0; i < 256; ++i) below[i] = bin[~(unsigned)i & 0xFFu];
 }
 
 }  // namespace lbpf
