@@ -107,8 +107,8 @@ def _traffic(kernel: str, launches_bytes: float | None):
 def main():
     args = _parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of this path is described in DESIGN.md and not run here.",
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); crops are "
+              "independent, so the path shards by crop, but no multi-GPU run is implemented.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -64,7 +64,7 @@ typedef enum lbpf_status {
     LBPF_E_INVALID = -1,     /* bad argument: NULL pointer, box outside its image, side < 3 ... */
     LBPF_E_BUDGET = -2,      /* request larger than the context's fixed capacity or budget */
     LBPF_E_HIP = -3,         /* a HIP runtime call failed; lbpf_last_error() has the detail */
-    LBPF_E_UNSUPPORTED = -4  /* valid request this build does not implement */
+    LBPF_E_UNSUPPORTED = -4  /* valid request the library does not implement */
 } lbpf_status;
 
 typedef enum lbpf_precision {
