@@ -734,8 +734,6 @@ __device__ void fast_crop(const CropDesc &cd, const FeatParams &fp, FastShared &
 
             Row6 A = make_row(rawA, lolo, span2, s8, s16);
             Row6 B = make_row(rawB, lolo, span2, s8, s16);
-            // One row: code the centre row B against A and C = the row in
-            // `slot`, count it, then refill `slot` kPF rows ahead.
             // Byte offsets of the next row to refill, kept running so the loop
             // has no multiplies; rows past h - 1 clamp to it (the offsets
             // grow with the row).
@@ -743,6 +741,8 @@ __device__ void fast_crop(const CropDesc &cd, const FeatParams &fp, FastShared &
             const uint32_t r0 = (uint32_t)(yb + 1 + kPF), rl = (uint32_t)(h - 1);
             uint32_t gnext = r0 * gstep + (uint32_t)xl, dnext = r0 * dstep + 2u * (uint32_t)xl;
             const uint32_t gmax = rl * gstep + (uint32_t)xl, dmax = rl * dstep + 2u * (uint32_t)xl;
+            // One row: code the centre row B against A and C = the row in
+            // `slot`, count it, then refill `slot` kPF rows ahead.
             auto step = [&](const int tt, RawRow &slot, const bool refill) {
                 const int yy = yb + tt;
                 const Row6 C = make_row(slot, lolo, span2, s8, s16);
