@@ -338,20 +338,6 @@ __device__ __forceinline__ u32x4 depth_chunk(const CropDesc &c, int y, int x0) {
 
 constexpr int kMedBatch = 8;  // 16-byte chunks in flight per thread
 
-// Ascending bitonic sort of one value per lane across a wave.
-__device__ __forceinline__ uint32_t wave_sort64(uint32_t x, int lane) {
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t y = __shfl_xor(x, j, 64);
-            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-            x = keep_min ? min(x, y) : max(x, y);
-        }
-    }
-    return x;
-}
-
 // One u16 pair of the median pass: per-half counts of v >= lo (ge2) and of
 // v != 0 (nz2), and the 1 mm window histogram of [lo, lo + 256). one2 holds
 // 0x10001 (kept opaque to the compiler, see crop_median_fast).
@@ -406,12 +392,23 @@ __device__ __forceinline__ int32_t median_finish(MedianScratch &ms, uint32_t *sh
 }
 
 // The 64-sample estimate of the median (wave 0 only): the lower median of the
-// non-zero values among `v` (one per lane), or 1000 when all are zero.
-__device__ __forceinline__ uint32_t median_estimate(uint32_t v, int lane) {
-    const uint32_t sorted = wave_sort64(v ? v : 0x10000u, lane);  // zeros last
+// non-zero values among `v` (one per lane), or 1000 when all are zero. A binary
+// search over the value range finds the smallest t with more than `rank`
+// non-zero samples <= t, each count a ballot (16 steps of one compare).
+__device__ __forceinline__ uint32_t median_estimate(uint32_t v) {
     const int nz = __popcll(__ballot(v != 0));
-    const uint32_t est = __shfl(sorted, nz > 0 ? (nz - 1) / 2 : 0, 64);
-    return nz > 0 ? est : 1000u;
+    if (nz == 0) return 1000u;
+    const uint32_t rank = (uint32_t)(nz - 1) / 2;
+    const uint32_t vm1 = v - 1u;  // v = 0 wraps above every bound
+    uint32_t lo = 1, hi = 65535;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint32_t)__popcll(__ballot(vm1 < mid)) > rank)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
 }
 
 // Exact lower median of the crop's non-zero depth, -1 if none.
@@ -442,7 +439,7 @@ __device__ __forceinline__ int32_t crop_median_fast(const CropDesc &c, MedianScr
     if (wave == 0) {
         const int sy = ((2 * (lane >> 3) + 1) * c.h) >> 4;
         const int sx = ((2 * (lane & 7) + 1) * c.w) >> 4;
-        const uint32_t est = median_estimate(c.depth[(size_t)sy * c.depth_pitch + sx], lane);
+        const uint32_t est = median_estimate(c.depth[(size_t)sy * c.depth_pitch + sx]);
         if (lane == 0) ms.rank = est;
     }
     __syncthreads();
