@@ -44,10 +44,12 @@
  *     use the context's scratch (reduced precision, argmax without caller
  *     scores, or FP32 products too small to fill the GPU, whose feature
  *     dimension is split over workgroups) are ordered across streams by an
- *     event the context keeps, so they never overlap each other; everything
- *     else may overlap. Inside a captured graph that ordering is the graph's,
- *     and a graph replay must not overlap eager scoring through the same
- *     context.
+ *     event the context keeps, so they never overlap each other; the plain
+ *     comparator calls (lbpf_features_plain, and lbpf_score_plain without
+ *     caller scores) are ordered the same way by events of their own;
+ *     everything else may overlap. Inside a captured graph that ordering is
+ *     the graph's, and a graph replay must not overlap eager scoring through
+ *     the same context.
  */
 #ifndef LBPF_H
 #define LBPF_H
@@ -317,7 +319,9 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
  * one-thread-per-pixel LBP kernel incrementing the crop's histogram with
  * global-memory atomics, and a normalisation kernel. Same arguments, results
  * (bit-exact) and errors as lbpf_features; counts_opt NULL uses a context
- * scratch row. Crops run in order on `stream`. */
+ * scratch row. Crops run in order on `stream`; every crop uses the context's
+ * median scratch, so calls queued on different streams run one after the
+ * other (ordered by an event the context keeps), never overlapped. */
 lbpf_status lbpf_features_plain(lbpf_ctx *ctx, const lbpf_image *images, int32_t n_images,
                                 const lbpf_box *boxes, int32_t n_boxes, float *hist,
                                 uint32_t *counts_opt, void *stream);

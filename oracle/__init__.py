@@ -271,7 +271,7 @@ def score_f64(X: np.ndarray, W: np.ndarray, b: np.ndarray, want_scores=True, n_t
     return S, am
 
 
-def train_ovr_f64(X: np.ndarray, labels: np.ndarray, K: int, C: float = 1.0, eps: float = 1e-3,
+def train_ovr_f64(X: np.ndarray, labels: np.ndarray, K: int, C: float = 1.0, eps: float = 1e-6,
                   max_epochs: int = 200, seed: int = 150401883, n_threads: int = 1):
     """One-vs-rest linear SVM (dual coordinate descent) in double.
 

@@ -56,6 +56,7 @@ struct lbpf_ctx {
     uint32_t *d_plain_counts = nullptr; // plain path: one crop's counts
     std::vector<CropDesc> h_crops;      // host staging of resolved boxes
     hipEvent_t scratch_ev = nullptr;    // last use of d_scores / d_xq / d_sx
+    hipEvent_t plain_ev = nullptr;      // last use of d_plain_median / d_plain_counts
     uint8_t *d_xq = nullptr;            // reduced-precision scoring: quantised feature rows
     float *d_sx = nullptr;              //   and their scales, kLpChunkRows rows
     size_t xq_bytes = 0;
@@ -235,6 +236,8 @@ lbpf_status lbpf_create(lbpf_ctx **out, const lbpf_feature_cfg *cfg, size_t hbm_
         return cleanup(fail_hip(e, "hipMalloc"));
     if ((e = hipEventCreateWithFlags(&ctx->scratch_ev, hipEventDisableTiming)) != hipSuccess)
         return cleanup(fail_hip(e, "hipEventCreate"));
+    if ((e = hipEventCreateWithFlags(&ctx->plain_ev, hipEventDisableTiming)) != hipSuccess)
+        return cleanup(fail_hip(e, "hipEventCreate"));
     if ((e = hipMalloc((void **)&ctx->d_part, kPartElems * sizeof(float))) != hipSuccess)
         return cleanup(fail_hip(e, "hipMalloc"));
     if ((e = hipMalloc((void **)&ctx->d_plain_median, sizeof(int32_t))) != hipSuccess)
@@ -258,6 +261,7 @@ void lbpf_destroy(lbpf_ctx *ctx) {
     if (ctx->d_scores) (void)hipFree(ctx->d_scores);
     if (ctx->d_plain_median) (void)hipFree(ctx->d_plain_median);
     if (ctx->scratch_ev) (void)hipEventDestroy(ctx->scratch_ev);
+    if (ctx->plain_ev) (void)hipEventDestroy(ctx->plain_ev);
     if (ctx->d_xq) (void)hipFree(ctx->d_xq);
     if (ctx->d_sx) (void)hipFree(ctx->d_sx);
     if (ctx->d_plain_counts) (void)hipFree(ctx->d_plain_counts);
@@ -503,15 +507,31 @@ lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, i
     const size_t wbytes = lp ? (size_t)K * lp_pitch(D, precision) + bbytes
                              : sizeof(float) * (size_t)K * D;
     // The first reduced-precision weights also size the context's feature
-    // quantisation scratch (kLpChunkRows rows at the widest pitch).
+    // quantisation scratch (kLpChunkRows rows at the widest pitch). Both of
+    // its buffers are allocated here, before the weights, and kept only as a
+    // pair: on any failure neither stays and the charge is refunded.
     const size_t xq_need =
-        (lp && !ctx->d_xq) ? (size_t)kLpChunkRows * lp_pitch(D, LBPF_BF16) : 0;
+        (lp && (!ctx->d_xq || !ctx->d_sx)) ? (size_t)kLpChunkRows * lp_pitch(D, LBPF_BF16) : 0;
     const size_t sx_need = xq_need ? sizeof(float) * kLpChunkRows : 0;
     if (!charge(ctx, wbytes + bbytes + xq_need + sx_need))
         return fail(LBPF_E_BUDGET, "weights exceed the HBM budget");
+    if (xq_need) {
+        uint8_t *xq = nullptr;
+        float *sx = nullptr;
+        hipError_t ea = hipMalloc((void **)&xq, xq_need);
+        if (ea == hipSuccess) ea = hipMalloc((void **)&sx, sx_need);
+        if (ea != hipSuccess) {
+            if (xq) (void)hipFree(xq);
+            ctx->used -= wbytes + bbytes + xq_need + sx_need;
+            return fail_hip(ea, "quantisation scratch");
+        }
+        ctx->d_xq = xq;
+        ctx->d_sx = sx;
+        ctx->xq_bytes = xq_need;
+    }
     lbpf_weights *w = new (std::nothrow) lbpf_weights();
     if (!w) {
-        ctx->used -= wbytes + bbytes + xq_need + sx_need;
+        ctx->used -= wbytes + bbytes;  // the scratch stays with the context
         return fail(LBPF_E_BUDGET, "out of host memory");
     }
     w->ctx = ctx;
@@ -530,11 +550,6 @@ lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, i
         if (e == hipSuccess) e = hipMalloc((void **)&w->Wq, (size_t)K * lp_pitch(D, precision));
         if (e == hipSuccess) e = hipMalloc((void **)&w->sw, bbytes);
         if (e == hipSuccess) e = launch_quant_rows(W, K, D, precision, w->Wq, w->sw, s);
-        if (e == hipSuccess && xq_need) {
-            e = hipMalloc((void **)&ctx->d_xq, xq_need);
-            if (e == hipSuccess) e = hipMalloc((void **)&ctx->d_sx, sx_need);
-            if (e == hipSuccess) ctx->xq_bytes = xq_need;
-        }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -838,14 +853,23 @@ lbpf_status lbpf_features_plain(lbpf_ctx *ctx, const lbpf_image *images, int32_t
     if (n_boxes > 0 && !hist) return fail(LBPF_E_INVALID, "hist is NULL");
     lbpf_status st = resolve(ctx, images, n_images, boxes, n_boxes, ctx->h_crops);
     if (st != LBPF_OK) return st;
+    if (n_boxes == 0) return LBPF_OK;
     hipStream_t s = (hipStream_t)stream;
     const size_t D = (size_t)ctx->fp.dim;
+    // Every crop uses the context's median word (and, without counts_opt, its
+    // counts row): calls on different streams are ordered by plain_ev so they
+    // never overlap. Under graph capture the graph's own order applies.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap), "hipStreamIsCapturing");
+    const bool order = cap == hipStreamCaptureStatusNone;
+    if (order) HIP_TRY(hipStreamWaitEvent(s, ctx->plain_ev, 0), "hipStreamWaitEvent");
     for (int32_t i = 0; i < n_boxes; ++i) {
         uint32_t *cnt = counts_opt ? counts_opt + (size_t)i * D : ctx->d_plain_counts;
         HIP_TRY(launch_plain_features(ctx->h_crops[(size_t)i], ctx->fp, ctx->d_bins,
                                       ctx->d_plain_median, cnt, hist + (size_t)i * D, s),
                 "plain feature launch");
     }
+    if (order) HIP_TRY(hipEventRecord(ctx->plain_ev, s), "hipEventRecord");
     return LBPF_OK;
 }
 
@@ -857,13 +881,21 @@ lbpf_status lbpf_score_plain(lbpf_ctx *ctx, const float *hist, int32_t N, const 
     if (!scores_opt && !argmax_opt) return fail(LBPF_E_INVALID, "no output requested");
     if (N > 0 && !hist) return fail(LBPF_E_INVALID, "hist is NULL");
     if (w->prec != LBPF_FP32) return fail(LBPF_E_UNSUPPORTED, "the plain path scores in FP32 only");
+    if (N == 0) return LBPF_OK;
     hipStream_t s = (hipStream_t)stream;
+    // Without caller scores every row goes through the context's score
+    // scratch, which lbpf_score also uses: ordered by scratch_ev like it.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap), "hipStreamIsCapturing");
+    const bool order = !scores_opt && cap == hipStreamCaptureStatusNone;
+    if (order) HIP_TRY(hipStreamWaitEvent(s, ctx->scratch_ev, 0), "hipStreamWaitEvent");
     for (int32_t n = 0; n < N; ++n) {
         float *srow = scores_opt ? scores_opt + (size_t)n * w->K : ctx->d_scores;
         HIP_TRY(launch_plain_score(hist + (size_t)n * w->D, w->W, w->b, w->K, w->D, srow,
                                    argmax_opt ? argmax_opt + n : nullptr, s),
                 "plain score launch");
     }
+    if (order) HIP_TRY(hipEventRecord(ctx->scratch_ev, s), "hipEventRecord");
     return LBPF_OK;
 }
 

@@ -368,7 +368,7 @@ class Context:
                                            _dptr(cnt), _stream()))
         return hist, cnt
 
-    def train(self, X: torch.Tensor, labels: torch.Tensor, K: int, C=1.0, eps=1e-3,
+    def train(self, X: torch.Tensor, labels: torch.Tensor, K: int, C=1.0, eps=1e-6,
               max_epochs=200, seed=150401883, alpha=None, warm=False, want_f64=False):
         """One-vs-rest SVM training on the device -> dict with W, b (FP32) and
         epochs [K]; W64 / b64 with want_f64; alpha (FP64 [K, N]) is updated in

@@ -46,6 +46,7 @@ class Request:
     t_done: float = 0.0
     argmax: np.ndarray | None = None
     scores: np.ndarray | None = None
+    features: np.ndarray | None = None  # [n, D] FP32 (backends asked to keep them)
     prev: "Request | None" = None     # previous frame of the same stream (tracking)
     owner: np.ndarray | None = None   # per box: index of the previous box it continues, or -1
     track_ids: np.ndarray | None = None
@@ -138,7 +139,8 @@ class GpuBackend:
     """Batched features + scores through liblbpf (fused path)."""
 
     def __init__(self, ctx, weights, n_slots: int, max_batch_frames: int, inflight: int = 2,
-                 keep_scores: bool = False, plain: bool = False, track: bool = False):
+                 keep_scores: bool = False, plain: bool = False, track: bool = False,
+                 keep_features: bool = False, keep_batches: int | None = None):
         import torch
         self.torch = torch
         self.ctx, self.weights, self.plain = ctx, weights, plain
@@ -147,6 +149,10 @@ class GpuBackend:
         self.last_req: dict[int, Request] = {}
         self.K = weights.K
         self.keep_scores = keep_scores
+        self.keep_features = keep_features
+        # Scores / features are copied back for the first keep_batches
+        # launches only (None: every launch).
+        self.keep_left = keep_batches
         dev = torch.device("cuda")
         self.grey = torch.empty((n_slots, 480, 640), dtype=torch.uint8, device=dev)
         self.depth = torch.empty((n_slots, 480, 640), dtype=torch.int16, device=dev)
@@ -164,7 +170,9 @@ class GpuBackend:
                 "O_host": torch.empty((max_boxes,), dtype=torch.int32).pin_memory(),
                 "S_host": (torch.empty((max_boxes, self.K), dtype=torch.float32).pin_memory()
                            if keep_scores else None),
-                "done": torch.cuda.Event(), "batch": None, "nb": 0})
+                "F_host": (torch.empty((max_boxes, ctx.dim), dtype=torch.float32).pin_memory()
+                           if keep_features else None),
+                "done": torch.cuda.Event(), "batch": None, "nb": 0, "kept": False})
         self.free_sets = collections.deque(range(inflight))
 
     def host_frame(self, grey: np.ndarray, depth: np.ndarray):
@@ -211,10 +219,15 @@ class GpuBackend:
             if self.track:
                 self._associate(batch, st, nb)
             st["A_host"][:nb].copy_(st["A"][:nb], non_blocking=True)
-            if self.keep_scores:
+            kept = self.keep_left is None or self.keep_left > 0
+            if self.keep_left is not None and self.keep_left > 0:
+                self.keep_left -= 1
+            if self.keep_scores and kept:
                 st["S_host"][:nb].copy_(st["S"][:nb], non_blocking=True)
+            if self.keep_features and kept:
+                st["F_host"][:nb].copy_(st["hist"][:nb], non_blocking=True)
             st["done"].record(s)
-        st["batch"], st["nb"] = batch, nb
+        st["batch"], st["nb"], st["kept"] = batch, nb, kept
 
     def _associate(self, batch: list[Request], st, nb: int):
         """Nearest-centre association of every frame in the batch with the
@@ -244,13 +257,17 @@ class GpuBackend:
             if st["batch"] is not None and st["done"].query():
                 t = time.perf_counter()
                 A = st["A_host"][:st["nb"]].numpy().copy()
-                S = st["S_host"][:st["nb"]].numpy().copy() if self.keep_scores else None
+                kept = st["kept"]
+                S = st["S_host"][:st["nb"]].numpy().copy() if self.keep_scores and kept else None
+                F = (st["F_host"][:st["nb"]].numpy().copy()
+                     if self.keep_features and kept else None)
                 O = st["O_host"][:st["nb"]].numpy().copy() if self.track else None
                 pos = 0
                 for req in st["batch"]:
                     n = len(req.boxes)
                     req.argmax = A[pos:pos + n]
                     req.scores = S[pos:pos + n] if S is not None else None
+                    req.features = F[pos:pos + n] if F is not None else None
                     if O is not None:  # owners index the call's track list
                         o = O[pos:pos + n]
                         req.owner = np.where(o >= 0, o - req.prev_off, -1)
@@ -330,14 +347,19 @@ def summarize(measured, wall: float) -> dict:
             "max_ms": float(lat.max())}
 
 
-def quick_latency(ctx, seconds: float = 3.0, warmup: float = 0.5) -> dict:
-    """A short run of the serving workload (16 streams x 30 fps, BF16 scores
-    against 1024 identities) for the headline line: p50/p99 frame latency of
-    the fused path and of the plain unbatched FP32 path on the same arrivals."""
+def quick_latency(ctx, seconds: float = 30.0, warmup: float = 2.0, plain_seconds: float = 10.0,
+                  pool: int = 24, keep_results: bool = False) -> dict:
+    """The serving workload for the headline line: 16 streams x 30 fps Poisson
+    arrivals, BF16 scores against 1024 identities, `warmup` + `seconds`
+    measured; then the plain unbatched FP32 path on the first `plain_seconds`
+    of the same arrivals. p50/p99 frame latency and crops/s of both. With
+    keep_results the fused run's features and scores are returned under
+    "_fused_results" (and the FP32 weights under "_weights") for an accuracy
+    statement against the FP64 oracle."""
     import torch
 
     from . import synth
-    n_streams, fps, K, pool = 16, 30.0, 1024, 8
+    n_streams, fps, K = 16, 30.0, 1024
     W, b = synth.synthetic_weights(K, ctx.dim, synth.W_SERVING)
     Wd, bd = torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda()
     w_bf16 = ctx.weights(Wd, bd, precision="bf16")
@@ -348,18 +370,29 @@ def quick_latency(ctx, seconds: float = 3.0, warmup: float = 0.5) -> dict:
         if (s, i % pool) not in raw:
             raw[(s, i % pool)] = synth.make_frame(s, i % pool, K)
     out = {"workload": f"serving: {n_streams} streams x {fps:.0f} fps Poisson, 640x480 frames, "
-                       f"1-8 faces, {K} identities, {seconds:.0f} s measured"}
-    for name, wts, plain in (("fused_bf16", w_bf16, False), ("plain_unbatched_fp32", w_fp32, True)):
-        be = GpuBackend(ctx, wts, 128, 64, inflight=2, plain=plain)
+                       f"1-8 faces (48-256 px, {pool} distinct frames per stream), {K} "
+                       f"identities; fused BF16: {warmup:.0f} s warm-up + {seconds:.0f} s; "
+                       f"plain FP32: the first {plain_seconds:.0f} s of the same arrivals"}
+    plain_arr = [a for a in arr if a[0] < warmup + plain_seconds]
+    for name, wts, plain, arrivals in (("fused_bf16", w_bf16, False, arr),
+                                       ("plain_unbatched_fp32", w_fp32, True, plain_arr)):
+        keep = keep_results and not plain
+        # Results are copied back only for the first 256 batches, which fall
+        # in the warm-up: the measured window carries no extra copies.
+        be = GpuBackend(ctx, wts, 128, 64, inflight=2, plain=plain, keep_scores=keep,
+                        keep_features=keep, keep_batches=256 if keep else None)
         frames = {}
-        for (_, s, i) in arr:
+        for (_, s, i) in arrivals:
             g, z, bx, ids = raw[(s, i % pool)]
             frames[(s, i)] = (be.host_frame(g, z), bx, ids)
         sch = Scheduler(128, 128 * FRAME_BYTES, max_batch_frames=64)
-        measured, wall, _ = run(be, sch, arr, frames, warmup)
+        measured, wall, reqs = run(be, sch, arrivals, frames, warmup)
         summ = summarize(measured, wall)
-        out[name] = {k: summ[k] for k in ("frames", "crops_per_s", "p50_ms", "p99_ms")
+        out[name] = {k: summ[k] for k in ("frames", "crops", "crops_per_s", "p50_ms", "p99_ms")
                      if k in summ}
+        if keep:
+            out["_fused_results"] = [r for r in reqs if r.features is not None]
+            out["_weights"] = (W, b)
     w_bf16.close()
     w_fp32.close()
     return out

@@ -128,12 +128,21 @@ def ragged_sizes(n: int, workload: int = W_RAGGED):
     return w.astype(np.int64), h
 
 
-def make_ragged(n: int, n_ident: int, workload: int = W_RAGGED, first_sample: int = 1000):
+def _render_range(args):
+    ws, hs, lo, hi, n_ident, workload, first_sample = args
+    return [render_crop(int(ws[i]), int(hs[i]), workload, i % n_ident, first_sample + i // n_ident)
+            for i in range(lo, hi)]
+
+
+def make_ragged(n: int, n_ident: int, workload: int = W_RAGGED, first_sample: int = 1000,
+                workers: int = 1):
     """n crops with ragged sizes packed into one grey and one depth pool.
 
     Returns (grey_pool u8 [P], depth_pool u16 [P], offsets i64 [n], sizes [n, 2]
     as (w, h), labels). Crop i occupies pool[offsets[i] : offsets[i] + w*h]
-    row-major with pitch w."""
+    row-major with pitch w. workers > 1 renders the crops in forked worker
+    processes (call it before the process touches the GPU); the result does
+    not depend on it."""
     ws, hs = ragged_sizes(n, workload)
     areas = ws * hs
     offsets = np.zeros(n, np.int64)
@@ -141,13 +150,22 @@ def make_ragged(n: int, n_ident: int, workload: int = W_RAGGED, first_sample: in
     total = int(areas.sum())
     grey = np.empty(total, np.uint8)
     depth = np.empty(total, np.uint16)
-    labels = np.empty(n, np.int32)
-    for i in range(n):
-        ident = i % n_ident
-        g, z = render_crop(int(ws[i]), int(hs[i]), workload, ident, first_sample + i // n_ident)
-        grey[offsets[i]: offsets[i] + areas[i]] = g.ravel()
-        depth[offsets[i]: offsets[i] + areas[i]] = z.ravel()
-        labels[i] = ident
+    labels = (np.arange(n) % n_ident).astype(np.int32)
+    step = max(1, -(-n // max(1, 4 * workers)))
+    jobs = [(ws, hs, lo, min(n, lo + step), n_ident, workload, first_sample)
+            for lo in range(0, n, step)]
+    if workers > 1 and n > 256:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_render_range, jobs)
+    else:
+        parts = [_render_range(j) for j in jobs]
+    i = 0
+    for part in parts:
+        for g, z in part:
+            grey[offsets[i]: offsets[i] + areas[i]] = g.ravel()
+            depth[offsets[i]: offsets[i] + areas[i]] = z.ravel()
+            i += 1
     return grey, depth, offsets, np.stack([ws, hs], axis=1), labels
 
 

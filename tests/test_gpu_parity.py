@@ -321,3 +321,35 @@ def test_plain_path_matches_oracle(ctx, ref):
     f, c, _ = ref.features(hp, boxes, n_threads=8)
     _assert_bitexact(hist.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), f, c)
     _check_scores(S.cpu().numpy(), A.cpu().numpy(), f, W, b, ref)
+
+
+def test_plain_path_two_streams(ctx, ref):
+    """Plain features (no caller counts: the context's median word and counts
+    row are shared) and argmax-only plain scoring queued for two different
+    frame sets on two streams at once: the calls are ordered by the context's
+    events, so both sets match the oracle bit for bit."""
+    W, b = synth.synthetic_weights(33, ctx.dim, synth.W_UNIFORM)
+    wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda())
+    sets = []
+    for k, side in enumerate((96, 112)):
+        g, z, _ = synth.make_crops(10, side, side, synth.W_UNIFORM, 256, first_sample=2000 + k)
+        planes, boxes = stacked_planes(g, z)
+        sets.append((g, z, planes, boxes))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    torch.cuda.synchronize()
+    for (g, z, planes, boxes), s in zip(sets, streams):
+        with torch.cuda.stream(s):
+            hist, _ = ctx.features_plain(planes, boxes)
+            _, A = ctx.score_plain(hist, wts, want_scores=False)
+            outs.append((hist, A))
+    torch.cuda.synchronize()
+    for (g, z, planes, boxes), (hist, A) in zip(sets, outs):
+        hp, _ = host_planes(g, z)
+        f, _, _ = ref.features(hp, boxes, n_threads=8)
+        assert np.array_equal(hist.cpu().numpy().view(np.uint32), f.view(np.uint32))
+        S64, A64 = ref.score_f64(f, W, b)
+        tol = score_tolerance(f, W, b)
+        top2 = np.sort(S64, axis=1)[:, -2:]
+        clear = (top2[:, 1] - top2[:, 0]) > 2 * tol.max(axis=1)
+        assert np.array_equal(A.cpu().numpy()[clear], A64[clear])

@@ -3,8 +3,9 @@ e4m3 with amax/448 row scales) on MFMA with FP32 accumulation.
 
 Parity: the GPU scores equal, within the FP32 accumulation bound (n * 2^-24
 of the condition scale, n the roundings in sequence), the exact FP64 dot
-product of operands quantised here in numpy by the documented rules
-(round to nearest even; FP8 saturating at 448). That pins the quantisation and
+product of operands quantised in numpy by the documented rules
+(tests/lp_ref.py: round to nearest even; FP8 saturating at 448; pinned against
+torch's own conversions). That pins the quantisation and
 the MFMA operand handling. Against the FP64 oracle on the unquantised data the
 error and the argmax agreement are reported (no pass bar beyond sanity)."""
 import numpy as np
@@ -13,62 +14,9 @@ import torch
 
 from paper_1504_01883_amd import lbpf, synth
 from tests.gpu_util import require_gpu, stacked_planes
+from tests.lp_ref import QUANT, lp_tolerance
 
 pytestmark = pytest.mark.gpu
-
-
-def q_bf16(x):
-    u = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
-    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
-    return (r.astype(np.uint32) << 16).view(np.float32).astype(np.float64), np.ones(x.shape[0])
-
-
-def q_f16(x):
-    amax = np.abs(x).max(axis=1)
-    e = np.where(amax > 0, np.frexp(amax)[1], 1)
-    sh = np.where(amax > 0, (e - 1) - 14, 0)
-    scale = np.ldexp(1.0, sh)
-    q = (x.astype(np.float64) / scale[:, None]).astype(np.float32).astype(np.float16)
-    return q.astype(np.float64), scale
-
-
-def _e4m3_values():
-    v = []
-    for code in range(0x7F):  # 0x00 .. 0x7E, non-negative finite
-        E, M = code >> 3, code & 7
-        v.append(M * 2.0 ** -9 if E == 0 else (1 + M / 8) * 2.0 ** (E - 7))
-    return np.array(v)
-
-
-E4M3 = _e4m3_values()
-
-
-def q_e4m3(x):
-    amax = np.abs(x).max(axis=1).astype(np.float32)
-    s = np.where(amax > 0, amax / np.float32(448.0), np.float32(1.0)).astype(np.float32)
-    y = (x.astype(np.float32) / s[:, None]).astype(np.float32)
-    a = np.minimum(np.abs(y).astype(np.float64), 448.0)
-    hi = np.clip(np.searchsorted(E4M3, a), 0, len(E4M3) - 1)
-    lo = np.clip(hi - 1, 0, len(E4M3) - 1)
-    dl, dh = a - E4M3[lo], E4M3[hi] - a
-    pick = np.where(dl < dh, lo, np.where(dh < dl, hi, np.where(lo % 2 == 0, lo, hi)))
-    return np.sign(y) * E4M3[pick], s.astype(np.float64)
-
-
-QUANT = {"bf16": q_bf16, "fp16": q_f16, "fp8": q_e4m3}
-
-# Products each MFMA instruction sums (32x32x16 for BF16/FP16, 32x32x64 for FP8).
-K_PER_MFMA = {"bf16": 16, "fp16": 16, "fp8": 64}
-
-
-def lp_tolerance(prec, D):
-    """Relative bound (to sum |x_q w_q| s_x s_w + |b|) on FP32 accumulation of
-    the exactly representable products: at most n = ceil(D / k) + k + 3
-    roundings in sequence (the FP32 accumulator over the D / k instructions,
-    the k products inside one, and the epilogue's scale product, scaling and
-    bias add), each contributing at most 2^-24, so n * 2^-24."""
-    k = K_PER_MFMA[prec]
-    return (-(-D // k) + k + 3) * 2.0 ** -24
 
 
 @pytest.fixture(scope="module")

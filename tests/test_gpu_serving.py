@@ -7,6 +7,7 @@ import torch
 
 from paper_1504_01883_amd import lbpf, serve, synth
 from tests.gpu_util import require_gpu
+from tests.lp_ref import lp_tolerance, quantised_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -25,9 +26,9 @@ def setup():
 
 
 def _serve(ctx, wts, frames, arrivals, n_slots=32, budget_frames=32, batch=16, inflight=2,
-           track=False):
+           track=False, keep_features=False):
     be = serve.GpuBackend(ctx, wts, n_slots, batch, inflight=inflight, keep_scores=True,
-                          track=track)
+                          track=track, keep_features=keep_features)
     handles = {}
     for (t, s, i) in arrivals:
         g, z, bx, ids = frames[i]
@@ -84,21 +85,27 @@ def test_alone_equals_mix(setup):
 
 
 def test_serving_matches_oracle(setup, ref):
+    """Frames served in one batch: every crop's FP32 features equal the
+    oracle's bit for bit, the BF16 scores equal the exact product of the
+    BF16-rounded operands within the FP32 accumulation tolerance, and the
+    argmax agrees with the FP64 oracle wherever its top-2 margin is clear of
+    the row's BF16 error."""
     ctx, wts, W, b, frames = setup
     arrivals = [(0.0, 0, i) for i in range(6)]
-    res, _ = _serve(ctx, wts, frames, arrivals)
+    res, _ = _serve(ctx, wts, frames, arrivals, keep_features=True)
+    tol = lp_tolerance("bf16", ctx.dim)
     for i in range(6):
         g, z, bx, _ = frames[i]
         boxes = [[0, int(x), int(y), int(w), int(h)] for (x, y, w, h) in bx]
         f, _, _ = ref.features([(g, z)], boxes, n_threads=8)
-        S64, A64 = ref.score_f64(f, W, b)
         got = res[i]
-        # BF16 scoring: errors are bounded by the operand rounding; compare the
-        # argmax where the oracle's margin is clear of it.
-        err = np.abs(got.scores - S64).max()
-        assert err < 0.05
+        assert np.array_equal(got.features.view(np.uint32), f.view(np.uint32))
+        qref, scale = quantised_reference(f, W, b, "bf16")
+        assert (np.abs(got.scores.astype(np.float64) - qref) <= tol * scale + 1e-30).all()
+        S64, A64 = ref.score_f64(f, W, b)
+        e_row = np.abs(got.scores - S64).max(axis=1)
         top2 = np.sort(S64, axis=1)[:, -2:]
-        clear = (top2[:, 1] - top2[:, 0]) > 4 * err
+        clear = (top2[:, 1] - top2[:, 0]) > 2 * e_row
         assert np.array_equal(got.argmax[clear], A64[clear])
 
 
