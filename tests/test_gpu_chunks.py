@@ -92,9 +92,11 @@ def test_lp_every_chunk_matches_quantised_reference(ctx, lp_data, prec):
     agree = float((A == A64).mean())
     print(f"{prec}: {N_LP} rows, max |S - S64| {np.abs(S - S64).max():.3e}, "
           f"argmax agreement {agree:.4f} ({clear.mean():.4f} of rows clear of the error)")
-    for c in range(3):  # every chunk has rows, and they agree with the oracle too
-        rows = slice(c * LP_CHUNK, min((c + 1) * LP_CHUNK, N_LP))
-        assert clear[rows].any()
+    # Each full chunk has rows clear of the error, so the oracle comparison
+    # above reaches every chunk (the one-row tail chunk is covered by the
+    # exact comparison alone: its row may sit within the error of a tie).
+    for c in range(2):
+        assert clear[c * LP_CHUNK:(c + 1) * LP_CHUNK].any()
 
 
 def test_fp32_argmax_only_multipass(ctx, ref):
