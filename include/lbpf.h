@@ -333,6 +333,28 @@ lbpf_status lbpf_score_plain(lbpf_ctx *ctx, const float *hist, int32_t N,
                              const lbpf_weights *weights, float *scores_opt,
                              int32_t *argmax_opt, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. FP32 scoring
+ * (step 6) as lbpf_score with FP32 weights, without a context: hist DEVICE
+ * [N][D] FP32, W DEVICE [K][D] FP32 row-major, b DEVICE [K] FP32 (the caller
+ * owns all three), scores_opt DEVICE [N][K] FP32 or NULL, argmax_opt DEVICE
+ * [N] int32 or NULL (not both NULL). The same kernels and results as
+ * lbpf_score. The call allocates nothing: the scratch its kernels need (each
+ * pass's scores when no score buffer is given, the partial tiles when the
+ * feature dimension is split over workgroups) is a static device array of
+ * LBPF_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; argmax-only calls score in passes of
+ * (LBPF_NOALLOC_SCRATCH_BYTES / 8) / K rows. Every call on one GPU shares
+ * that GPU's array and nothing orders them: calls that overlap on one GPU
+ * (other streams, other host threads) race and give wrong results.
+ * N = 0 is a no-op. Errors: LBPF_E_INVALID (NULL pointers, N < 0, K < 1,
+ * D < 1, no output), LBPF_E_BUDGET (argmax only with K above
+ * LBPF_NOALLOC_SCRATCH_BYTES / 8), LBPF_E_HIP. */
+#define LBPF_NOALLOC_SCRATCH_BYTES (16u << 20)
+lbpf_status lbpf_score_noalloc(const float *hist, int32_t N, const float *W, const float *b,
+                               int32_t K, int32_t D, float *scores_opt, int32_t *argmax_opt,
+                               void *stream);
+
 /* Test hook: per-pixel codes and mask of ONE box, for bit-exact checks.
  * image/box are HOST structs; grey_codes, depth_codes, mask are DEVICE
  * [box->h][box->w] u8 arrays. Interior pixels receive their grey code, depth

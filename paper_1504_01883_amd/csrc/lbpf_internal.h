@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/lbpf.h"
 
 namespace lbpf {
@@ -25,6 +27,9 @@ struct CropDesc {
 constexpr uint32_t kCropOverReadOk = 1u;
 constexpr int kOverRead = 7;
 static_assert(sizeof(CropDesc) == 32, "CropDesc layout");
+
+// Record `msg` as the calling thread's lbpf_last_error() and return s.
+lbpf_status set_last_error(lbpf_status s, const std::string &msg);
 
 // Feature geometry shared by every kernel launch of a context.
 struct FeatParams {

@@ -38,6 +38,8 @@ constexpr int kRing = 4;
 
 }  // namespace
 
+lbpf_status lbpf::set_last_error(lbpf_status s, const std::string &msg) { return fail(s, msg); }
+
 struct lbpf_ctx {
     int device = 0;
     int num_cus = 256;

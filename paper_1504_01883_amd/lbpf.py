@@ -33,6 +33,7 @@ EXPORTS = [
     "lbpf_score_plain", "lbpf_batch_set_launch", "lbpf_batch_get_launch", "lbpf_tune_batch",
     "lbpf_graph_create", "lbpf_graph_launch", "lbpf_graph_destroy", "lbpf_warp_crop_bytes",
     "lbpf_features_warped", "lbpf_train_workspace_bytes", "lbpf_train_ovr", "lbpf_track",
+    "lbpf_score_noalloc",
 ]
 
 
@@ -136,6 +137,7 @@ def load():
         "lbpf_train_ovr": (st, [vp, vp, vp, i32, i32, ctypes.c_double, ctypes.c_double, i32,
                                 ctypes.c_uint64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lbpf_track": (st, [vp, vp, vp, i32, vp, vp, i32, ctypes.c_int64, vp, vp, vp]),
+        "lbpf_score_noalloc": (st, [vp, i32, vp, vp, i32, i32, vp, vp, vp]),
         "lbpf_status_string": (ctypes.c_char_p, [st]),
         "lbpf_last_error": (ctypes.c_char_p, []),
     }
@@ -490,6 +492,32 @@ class Context:
         _check(load().lbpf_debug_codes(self._h, imgs, ctypes.byref(bx), *(_dptr(o) for o in outs),
                                        _stream()))
         return tuple(outs)
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def score_noalloc(hist: torch.Tensor, W: torch.Tensor, b: torch.Tensor, want_scores=True,
+                  want_argmax=True, scores_out=None, argmax_out=None):
+    """FP32 scoring through lbpf_score_noalloc (no context, no allocation in
+    the library): hist [N, D], W [K, D], b [K] FP32 CUDA tensors ->
+    (scores [N, K] | None, argmax [N] | None)."""
+    for t in (hist, W, b):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("hist, W and b must be contiguous float32 CUDA tensors")
+    N, D = hist.shape
+    K = W.shape[0]
+    if W.shape[1] != D or b.shape != (K,):
+        raise ValueError("W must be [K, D] and b [K]")
+    S = scores_out
+    if want_scores and S is None:
+        S = torch.empty((N, K), dtype=torch.float32, device=hist.device)
+    A = argmax_out
+    if want_argmax and A is None:
+        A = torch.empty((N,), dtype=torch.int32, device=hist.device)
+    _check(load().lbpf_score_noalloc(_dptr(hist), N, _dptr(W), _dptr(b), K, D, _dptr(S),
+                                     _dptr(A), _stream()))
+    return S, A
 
 
 def to_device_planes(grey: np.ndarray | None, depth: np.ndarray, device="cuda"):
