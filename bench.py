@@ -75,6 +75,10 @@ def _parse():
     p.add_argument("--precision-rows", type=int, default=131072)
     p.add_argument("--precision-identities", type=int, default=8192)
     p.add_argument("--ragged-crops", type=int, default=RAGGED_CROPS)
+    p.add_argument("--launch", default=None,
+                   help="ragged batch: fixed feature launch shape persistent,wg_per_cu,"
+                        "row_prefetch,sorted (e.g. 1,4,4,1) instead of the autotuner, so a "
+                        "profiled run has no tuning trials")
     p.add_argument("--serve-seconds", type=float, default=30.0)
     p.add_argument("--serve-warmup", type=float, default=2.0)
     return p.parse_args()
@@ -200,7 +204,12 @@ def run_ragged(args, ctx, host):
     S = torch.empty((n, K), dtype=torch.float32, device="cuda")
     A = torch.empty((n,), dtype=torch.int32, device="cuda")
     area = float((sizes[:, 0] * sizes[:, 1]).mean())
-    tuned = tune.tuned(ctx, batch, hist, n, area, reps=3, retune=True)
+    if args.launch:
+        p, m, pf, so = (int(v) for v in args.launch.split(","))
+        batch.set_launch(persistent=p, wg_per_cu=m, row_prefetch=pf, sorted=so)
+        tuned = {"cfg": batch.get_launch(), "us": None, "cached": False, "fixed": True}
+    else:
+        tuned = tune.tuned(ctx, batch, hist, n, area, reps=3, retune=True)
     graph = ctx.graph(batch, hist)  # the feature launch, captured once
 
     def step(i, ev):
@@ -726,11 +735,27 @@ def bench_precision(args):
         tf = flops / (ms * 1e-3) / 1e12
         idx = torch.from_numpy(sample).cuda()
         got[prec] = (S[idx].double().cpu().numpy(), A[idx].cpu().numpy())
+        # The same call asking for the argmax only (no score matrix written).
+        A2 = torch.empty_like(A)
+        ctx.score(X, wts, want_scores=False, argmax_out=A2)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(A2, A))
+        e[0].record()
+        for _ in range(steps):
+            ctx.score(X, wts, want_scores=False, argmax_out=A2)
+        e[1].record()
+        torch.cuda.synchronize()
+        ms_a = e[0].elapsed_time(e[1]) / steps
+        tf_a = flops / (ms_a * 1e-3) / 1e12
         res[prec] = {"ms": ms, "tflops": tf, "peak_tflops": PEAKS_TFLOPS[prec],
                      "mfma_frac": tf / PEAKS_TFLOPS[prec],
                      "includes": "feature-row quantisation + GEMM + argmax" if prec != "fp32"
-                                 else "GEMM + argmax"}
-        print(f"[bench] {prec}: {ms:.2f} ms, {tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
+                                 else "GEMM + argmax",
+                     "argmax_only": {"ms": ms_a, "tflops": tf_a,
+                                     "mfma_frac": tf_a / PEAKS_TFLOPS[prec],
+                                     "argmax_equal_to_with_scores": same}}
+        print(f"[bench] {prec}: {ms:.2f} ms, {tf:.1f} TFLOP/s; argmax only {ms_a:.2f} ms",
+              file=sys.stderr, flush=True)
         wts.close()
     Xs = X[torch.from_numpy(sample).cuda()].cpu().numpy()
     cpu = None
