@@ -77,9 +77,14 @@ hipError_t launch_plain_score(const float *x, const float *W, const float *b, in
 int32_t lp_pitch(int32_t D, int32_t mode);
 hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mode, uint8_t *out,
                              float *scales, hipStream_t s);
+// S: [N][K] scores, or null for argmax only; argmax: [N] or null. scratch
+// (scratch_elems floats) holds the per-tile argmax pairs, or the scores when
+// S is null and the pairs do not fit; it must hold N * K floats when S is
+// null and 2 N ceil(K / 256) does not fit.
 hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const uint8_t *Wq,
                            const float *sw, const float *b, int32_t K, int32_t D, int32_t mode,
-                           float *S, hipStream_t s);
+                           float *S, int32_t *argmax, float *scratch, size_t scratch_elems,
+                           hipStream_t s);
 
 // Warped crops (warp.hip): each crop is sampled from its planes through two
 // 16.16 fixed-point affine frames into a staging crop of pitch w, which the

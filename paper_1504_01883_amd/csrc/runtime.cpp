@@ -606,23 +606,25 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
     for (int32_t n0 = 0; n0 < N; n0 += rows) {
         const int32_t n = std::min(rows, N - n0);
         float *S = scores_opt ? scores_opt + (size_t)n0 * K : ctx->d_scores;
-        if (w->prec == LBPF_FP32) {
-            const int32_t sp = n == std::min(rows, N)
-                                   ? splits
-                                   : score_f32_splits(n, w->K, w->D, ctx->num_cus, kPartElems);
-            HIP_TRY(launch_score_f32(hist + (size_t)n0 * D, n, w->W, w->b, w->K, w->D, S,
-                                     argmax_opt ? argmax_opt + n0 : nullptr, s, sp, ctx->d_part),
-                    "score launch");
-        } else {
+        if (w->prec != LBPF_FP32) {
             HIP_TRY(launch_quant_rows(hist + (size_t)n0 * D, n, w->D, w->prec, ctx->d_xq,
                                       ctx->d_sx, s),
                     "quantise launch");
+            // The argmax comes from the GEMM's epilogue where it can; the
+            // scratch then holds its per-tile pairs (and S nothing).
             HIP_TRY(launch_score_lp(ctx->d_xq, ctx->d_sx, n, w->Wq, w->sw, w->b, w->K, w->D,
-                                    w->prec, S, s),
+                                    w->prec, scores_opt ? S : nullptr,
+                                    argmax_opt ? argmax_opt + n0 : nullptr, ctx->d_scores,
+                                    ctx->scores_elems, s),
                     "score launch");
-            if (argmax_opt)
-                HIP_TRY(launch_argmax(S, n, w->K, argmax_opt + n0, s), "argmax launch");
+            continue;
         }
+        const int32_t sp = n == std::min(rows, N)
+                               ? splits
+                               : score_f32_splits(n, w->K, w->D, ctx->num_cus, kPartElems);
+        HIP_TRY(launch_score_f32(hist + (size_t)n0 * D, n, w->W, w->b, w->K, w->D, S,
+                                 argmax_opt ? argmax_opt + n0 : nullptr, s, sp, ctx->d_part),
+                "score launch");
     }
     if (order) HIP_TRY(hipEventRecord(ctx->scratch_ev, s), "hipEventRecord");
     return LBPF_OK;

@@ -9,9 +9,16 @@
 //   FP8 : OCP e4m3 (bias 7, max 448, no infinities), per-row scale
 //         s = amax / 448, x / s rounded to nearest even and saturated.
 // Quantised rows are stored with a row pitch rounded up to 128 bytes, zero
-// padded, so every k-stage of the GEMM is a whole 128-byte chunk.
+// padded, so every k-stage of the GEMM is a whole 128-byte chunk. Rows of up
+// to 8192 values are quantised by k_quant_rows_vec in one read (the row held
+// in registers, vector stores), longer ones by k_quant_rows.
 //
-// GEMM: a workgroup of 4 wave64 owns a 256 (n) x 128 (k) tile of S; wave w
+// Large products (N >= 512, K >= 256) run k_score_lp_big (256 x 256 tiles
+// through an LDS ring, described there), whose epilogue also reduces each
+// row's best identity over the tile; k_argmax_tiles merges the tiles, so an
+// argmax-only call never writes S.
+//
+// Small products, GEMM: a workgroup of 4 wave64 owns a 256 (n) x 128 (k) tile of S; wave w
 // owns rows 128 (w & 1) .. +128 and columns 64 (w >> 1) .. +64 as 4 x 2
 // blocks of 32 x 32 (v_mfma_f32_32x32x16_{bf16,f16} or
 // v_mfma_f32_32x32x64_f8f6f4). Per k-stage of 128 bytes per row the
@@ -78,6 +85,22 @@ __device__ __forceinline__ uint8_t to_e4m3_rne_sat(float f) {
     return (uint8_t)(sign | bits);
 }
 
+// The same encoding with integer rounding: for a >= 2^-6 (normal e4m3) the
+// FP32 pattern keeps its exponent and top 3 mantissa bits, rounded to nearest
+// even by adding 0x7FFFF plus the lowest kept bit, then rebiased (FP32
+// exponent bias 127, e4m3 bias 7); below 2^-6 the value is a multiple of
+// 2^-9 rounded to nearest even by one rint (8 lands on 0x08, the smallest
+// normal, as it should).
+__device__ __forceinline__ uint32_t e4m3_bits(float f) {
+    const uint32_t sign = (__float_as_uint(f) >> 24) & 0x80u;
+    const float a = fabsf(f);
+    if (!(a < 448.0f)) return sign | 0x7Eu;  // saturate (NaN too) to 448
+    if (a < 0.015625f) return sign | (uint32_t)rintf(a * 512.0f);
+    const uint32_t u = __float_as_uint(a);
+    const uint32_t r = u + 0x7FFFFu + ((u >> 20) & 1u);
+    return sign | min((r >> 20) - (120u << 3), 0x7Eu);
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
@@ -116,6 +139,78 @@ __global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ X,
         const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
         if (threadIdx.x == 0) scales[r] = s;
         for (int i = threadIdx.x; i < pitch; i += 256) o[i] = i < D ? to_e4m3_rne_sat(x[i] / s) : 0;
+    }
+}
+
+// One wave per row, four rows per workgroup, for rows of D <= 256 kC values
+// with D % 4 == 0 and 16-byte aligned rows: the row is read once into
+// registers (float4 per lane and chunk), its amax reduced over the wave, and
+// the converted values stored as one 8-byte (BF16, FP16) or 4-byte (FP8)
+// vector per float4; the pad up to `pitch` is zeroed. Same values and scales
+// as k_quant_rows.
+template <int kMode, int kC>
+__global__ __launch_bounds__(256) void k_quant_rows_vec(const float *__restrict__ X, int32_t rows,
+                                                        int32_t D, int32_t pitch,
+                                                        uint8_t *__restrict__ out,
+                                                        float *__restrict__ scales) {
+    const int lane = threadIdx.x & 63;
+    const int32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const int nq = D >> 2;
+    const f32x4 *x = reinterpret_cast<const f32x4 *>(X + (size_t)r * D);
+    f32x4 v[kC];
+    float amax = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kC; ++c) {
+        const int q = c * 64 + lane;
+        v[c] = q < nq ? __builtin_nontemporal_load(x + q) : f32x4{0.f, 0.f, 0.f, 0.f};
+        amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v[c].x), fabsf(v[c].y)),
+                                 fmaxf(fabsf(v[c].z), fabsf(v[c].w))));
+    }
+    amax = wave_max(amax);
+    uint8_t *o = out + (size_t)r * pitch;
+    constexpr int kEB = kMode == LBPF_FP8_E4M3 ? 1 : 2;
+    if constexpr (kMode == LBPF_FP8_E4M3) {
+        const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
+        if (lane == 0) scales[r] = s;
+#pragma unroll
+        for (int c = 0; c < kC; ++c) {
+            const int q = c * 64 + lane;
+            if (q < nq) {
+                const uint32_t w = e4m3_bits(v[c].x / s) | (e4m3_bits(v[c].y / s) << 8) |
+                                   (e4m3_bits(v[c].z / s) << 16) | (e4m3_bits(v[c].w / s) << 24);
+                *reinterpret_cast<uint32_t *>(o + 4 * q) = w;
+            }
+        }
+    } else {
+        int sh = 0;
+        if constexpr (kMode == LBPF_FP16) {
+            int e = 0;
+            if (amax > 0.0f) frexpf(amax, &e);  // amax in [2^(e-1), 2^e)
+            sh = (amax > 0.0f) ? (e - 1) - 14 : 0;
+            if (lane == 0) scales[r] = ldexpf(1.0f, sh);
+        } else {
+            if (lane == 0) scales[r] = 1.0f;
+        }
+        auto cvt = [&](float f) -> uint32_t {
+            if constexpr (kMode == LBPF_FP16) return to_f16_rne(ldexpf(f, -sh));
+            else return to_bf16_rne(f);
+        };
+#pragma unroll
+        for (int c = 0; c < kC; ++c) {
+            const int q = c * 64 + lane;
+            if (q < nq) {
+                const uint32_t lo = cvt(v[c].x) | (cvt(v[c].y) << 16);
+                const uint32_t hi = cvt(v[c].z) | (cvt(v[c].w) << 16);
+                *reinterpret_cast<uint2 *>(o + 8 * q) = uint2{lo, hi};
+            }
+        }
+    }
+    // Zero pad: elements D .. pitch / kEB - 1, four at a time (pitch is a
+    // multiple of 128 bytes and D of 4).
+    for (int q = nq + lane; q < pitch / (4 * kEB); q += 64) {
+        if constexpr (kEB == 1) *reinterpret_cast<uint32_t *>(o + 4 * q) = 0u;
+        else *reinterpret_cast<uint2 *>(o + 8 * q) = uint2{0u, 0u};
     }
 }
 
@@ -338,6 +433,13 @@ __device__ __forceinline__ void copy_stage(const uint8_t *__restrict__ Xq, int32
 
 // kW waves (4: one per SIMD, each 128 x 128 of the tile; 8: two per SIMD,
 // each 128 x 64, so one wave's waits are covered by the other's MFMAs).
+// The blocks are multiplied with the weight tile as the MFMA's first operand,
+// so each holds a 32 x 32 block of S transposed (identities x feature rows):
+// every lane then holds 16 identities of one feature row, and the per-row
+// argmax over the tile is mostly in-register work. S may be null (argmax
+// only); apart, when not null, receives each row's (best score, identity)
+// over the tile's 256 identities: values at apart[n KT + t], identities (as
+// int32) at apart[N KT + n KT + t], t = k0 / 256, KT = ceil(K / 256).
 template <int kMode, int kW>
 __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restrict__ Xq,
                                                           const float *__restrict__ sx, int32_t N,
@@ -345,7 +447,8 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
                                                           const float *__restrict__ sw,
                                                           const float *__restrict__ bias,
                                                           int32_t K, int32_t pitch,
-                                                          float *__restrict__ S) {
+                                                          float *__restrict__ S,
+                                                          float *__restrict__ apart) {
     constexpr int kCW = kBigT / (kW / 2);  // identities per wave
     constexpr int kJB = kCW / 32;          // 32-wide blocks per wave
     constexpr int kCopies = 2 * (kBigT / kW / 16);
@@ -403,7 +506,7 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < kJB; ++j)
-                    acc[i][j] = mfma_step<kMode>(f.a[i], f.b[j], acc[i][j], sub);
+                    acc[i][j] = mfma_step<kMode>(f.b[j], f.a[i], acc[i][j], sub);
     };
     // Iteration st: make stage st + 1 visible, start copying stage
     // st + kStages - 1 into the buffer of stage st - 1 (read an iteration
@@ -470,24 +573,130 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
     }
     }
 
-    // 32 x 32 block layout: lane l, register r holds row 8 (r / 4) + 4 (l / 32)
-    // + r % 4 and column l % 32.
+    // Transposed 32 x 32 block layout: lane l, register r of acc[i][j] holds
+    // feature row 32 i + l % 32 of the wave's rows and identity
+    // 32 j + 8 (r / 4) + 4 (l / 32) + r % 4 of its identities. Each lane scans
+    // its identities in increasing order keeping the first maximum, then
+    // meets lane l ^ 32 (the other identities of the same row).
+    const int32_t kw = k0 + wn * kCW;
+    const bool vec4 = (K & 3) == 0;
+    // This lane's identities are the same for every row block: their scales
+    // and biases are loaded once.
+    float swv[kJB][16], bsv[kJB][16];
 #pragma unroll
-    for (int j = 0; j < kJB; ++j) {
-        const int32_t k = k0 + wn * kCW + 32 * j + (lane & 31);
-        if (k >= K) continue;
-        const float swk = sw[k], bk = bias[k];
+    for (int j = 0; j < kJB; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int r = 0; r < 16; ++r) {
+            const int32_t k = kw + 32 * j + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            swv[j][r] = k < K ? sw[k] : 0.0f;
+            bsv[j][r] = k < K ? bias[k] : 0.0f;
+        }
+    float best[4];
+    int32_t barg[4];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int32_t n = n0 + wm * 128 + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (n < N) S[(size_t)n * K + k] = (sx[n] * swk) * acc[i][j][r] + bk;
+    for (int i = 0; i < 4; ++i) {
+        const int32_t n = n0 + wm * 128 + 32 * i + (lane & 31);
+        const float sxn = n < N ? sx[n] : 0.0f;
+        best[i] = -INFINITY;
+        barg[i] = K;  // no identity yet
+#pragma unroll
+        for (int j = 0; j < kJB; ++j)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int32_t kg = kw + 32 * j + 8 * g + 4 * (lane >> 5);
+                f32x4 v;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int32_t k = kg + t;
+                    if (k < K) {
+                        v[t] = (sxn * swv[j][4 * g + t]) * acc[i][j][4 * g + t] + bsv[j][4 * g + t];
+                        if (v[t] > best[i] || barg[i] == K) {
+                            best[i] = v[t];
+                            barg[i] = k;
+                        }
+                    }
+                }
+                if (S && n < N) {
+                    float *row = S + (size_t)n * K;
+                    if (vec4 && kg + 3 < K) {
+                        *reinterpret_cast<f32x4 *>(row + kg) = v;
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            if (kg + t < K) row[kg + t] = v[t];
+                    }
+                }
             }
+        const float ob = __shfl_xor(best[i], 32, 64);
+        const int32_t oa = __shfl_xor(barg[i], 32, 64);
+        if (ob > best[i] || (ob == best[i] && oa < barg[i])) {
+            best[i] = ob;
+            barg[i] = oa;
+        }
+    }
+    if (!apart) return;
+    // The kW / 2 waves of a row half cover the tile's identities in
+    // increasing ranges: merge them through LDS (the ring is no longer read
+    // once every wave has passed this barrier).
+    __syncthreads();
+    float *red_v = reinterpret_cast<float *>(lds);                 // [2][kW / 2][128]
+    int32_t *red_i = reinterpret_cast<int32_t *>(lds + 4 * 128 * kW);
+    if (lane < 32) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            red_v[(wm * (kW / 2) + wn) * 128 + 32 * i + lane] = best[i];
+            red_i[(wm * (kW / 2) + wn) * 128 + 32 * i + lane] = barg[i];
+        }
+    }
+    __syncthreads();
+    const int32_t kt_n = (int32_t)KT, kt = k0 / kBigT;
+    for (int rr = tid; rr < kBigT; rr += 64 * kW) {
+        const int h = rr >> 7, q = rr & 127;
+        float bv = -INFINITY;
+        int32_t bi = K;
+#pragma unroll
+        for (int w = 0; w < kW / 2; ++w) {
+            const float v = red_v[(h * (kW / 2) + w) * 128 + q];
+            const int32_t a = red_i[(h * (kW / 2) + w) * 128 + q];
+            if (v > bv || (v == bv && a < bi)) {
+                bv = v;
+                bi = a;
+            }
+        }
+        const int32_t n = n0 + rr;
+        if (n < N) {
+            apart[(size_t)n * kt_n + kt] = bv;
+            reinterpret_cast<int32_t *>(apart)[(size_t)N * kt_n + (size_t)n * kt_n + kt] = bi;
+        }
     }
 }
 
+// Merge of the per-tile (best score, identity) pairs of k_score_lp_big, one
+// thread per row: tiles in increasing identity order, a strict > keeps the
+// lowest identity among equal scores.
+__global__ __launch_bounds__(256) void k_argmax_tiles(const float *__restrict__ apart, int32_t N,
+                                                      int32_t KT, int32_t *__restrict__ out) {
+    const int32_t n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    const float *pv = apart + (size_t)n * KT;
+    const int32_t *pi = reinterpret_cast<const int32_t *>(apart) + (size_t)N * KT + (size_t)n * KT;
+    float bv = pv[0];
+    int32_t bi = pi[0];
+    for (int32_t t = 1; t < KT; ++t) {
+        const float v = pv[t];
+        if (v > bv) {
+            bv = v;
+            bi = pi[t];
+        }
+    }
+    out[n] = bi;
+}
+
 }  // namespace
+
+// float4 chunks per lane of the register-resident quantiser: rows up to
+// 8192 values.
+constexpr int kQuantChunks = 32;
 
 int32_t lp_pitch(int32_t D, int32_t mode) {
     const int32_t bytes = D * (mode == LBPF_FP8_E4M3 ? 1 : 2);
@@ -498,6 +707,19 @@ hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mo
                              float *scales, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     const int32_t pitch = lp_pitch(D, mode);
+    if (D % 4 == 0 && D <= 256 * kQuantChunks && ((uintptr_t)X & 15) == 0) {
+        const dim3 grid((rows + 3) / 4);
+        if (mode == LBPF_BF16)
+            hipLaunchKernelGGL((k_quant_rows_vec<LBPF_BF16, kQuantChunks>), grid, dim3(256), 0, s,
+                               X, rows, D, pitch, out, scales);
+        else if (mode == LBPF_FP16)
+            hipLaunchKernelGGL((k_quant_rows_vec<LBPF_FP16, kQuantChunks>), grid, dim3(256), 0, s,
+                               X, rows, D, pitch, out, scales);
+        else
+            hipLaunchKernelGGL((k_quant_rows_vec<LBPF_FP8_E4M3, kQuantChunks>), grid, dim3(256), 0,
+                               s, X, rows, D, pitch, out, scales);
+        return hipGetLastError();
+    }
     if (mode == LBPF_BF16)
         hipLaunchKernelGGL(k_quant_rows<LBPF_BF16>, dim3(rows), dim3(256), 0, s, X, rows, D, pitch,
                            out, scales);
@@ -512,24 +734,37 @@ hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mo
 
 hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const uint8_t *Wq,
                            const float *sw, const float *b, int32_t K, int32_t D, int32_t mode,
-                           float *S, hipStream_t s) {
+                           float *S, int32_t *argmax, float *scratch, size_t scratch_elems,
+                           hipStream_t s) {
     if (N <= 0 || K <= 0) return hipSuccess;
     const int32_t pitch = lp_pitch(D, mode);
     if (N >= 2 * kBigT && K >= kBigT) {
-        // Large products: 256 x 256 tiles fed through the LDS ring.
-        dim3 grid(((K + kBigT - 1) / kBigT) * ((N + kBigT - 1) / kBigT));
+        // Large products: 256 x 256 tiles fed through the LDS ring, the
+        // argmax taken in the epilogue (per tile) when its pairs fit the
+        // scratch, else by a pass over the scores.
+        const int32_t KT = (K + kBigT - 1) / kBigT;
+        const bool fuse = argmax && 2 * (size_t)N * KT <= scratch_elems;
+        float *Sout = S ? S : (fuse ? nullptr : scratch);
+        float *apart = fuse ? scratch : nullptr;
+        dim3 grid((uint32_t)KT * ((N + kBigT - 1) / kBigT));
         constexpr int kW = kBigWaves;
         if (mode == LBPF_BF16)
             hipLaunchKernelGGL((k_score_lp_big<LBPF_BF16, kW>), grid, dim3(64 * kW), 0, s, Xq, sx,
-                               N, Wq, sw, b, K, pitch, S);
+                               N, Wq, sw, b, K, pitch, Sout, apart);
         else if (mode == LBPF_FP16)
             hipLaunchKernelGGL((k_score_lp_big<LBPF_FP16, kW>), grid, dim3(64 * kW), 0, s, Xq, sx,
-                               N, Wq, sw, b, K, pitch, S);
+                               N, Wq, sw, b, K, pitch, Sout, apart);
         else
             hipLaunchKernelGGL((k_score_lp_big<LBPF_FP8_E4M3, kW>), grid, dim3(64 * kW), 0, s, Xq,
-                               sx, N, Wq, sw, b, K, pitch, S);
+                               sx, N, Wq, sw, b, K, pitch, Sout, apart);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !argmax) return e;
+        if (!fuse) return launch_argmax(Sout, N, K, argmax, s);
+        hipLaunchKernelGGL(k_argmax_tiles, dim3((N + 255) / 256), dim3(256), 0, s, apart, N, KT,
+                           argmax);
         return hipGetLastError();
     }
+    if (!S) S = scratch;
     dim3 grid(((K + kTN - 1) / kTN) * ((N + kTM - 1) / kTM));
     if (mode == LBPF_BF16)
         hipLaunchKernelGGL(k_score_lp<LBPF_BF16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,
@@ -540,7 +775,9 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
     else
         hipLaunchKernelGGL(k_score_lp<LBPF_FP8_E4M3>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b,
                            K, pitch, S);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !argmax) return e;
+    return launch_argmax(S, N, K, argmax, s);
 }
 
 }  // namespace lbpf
