@@ -310,16 +310,22 @@ __device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
 }
 
 // Depth pixels x0..x0+7 of crop row y as four u16 pairs; pixels at x >= w
-// read as 0.
+// read as 0. A chunk that ends past the right edge of a crop that may not be
+// over-read is loaded from column w - 8 instead (crops at least 8 wide), and
+// the pixels before x0 are zeroed as well: the median pass does not count a
+// zero, so every pixel still counts once, and the chunk is one load.
 __device__ __forceinline__ u32x4 depth_chunk(const CropDesc &c, int y, int x0) {
-    if ((c.flags & kCropOverReadOk) || x0 + 8 <= c.w) {
-        u32x4 q = gld<u32x4>(c.depth, ((uint32_t)y * (uint32_t)c.depth_pitch + (uint32_t)x0) * 2u);
+    const bool inside = (c.flags & kCropOverReadOk) || x0 + 8 <= c.w;
+    if (inside || c.w >= 8) {
+        const int xs = inside ? x0 : c.w - 8;
+        u32x4 q = gld<u32x4>(c.depth, ((uint32_t)y * (uint32_t)c.depth_pitch + (uint32_t)xs) * 2u);
         if (x0 + 8 > c.w) {
-            const int valid = c.w - x0;  // 1..7
+            // Element e (column xs + e) is kept iff x0 <= xs + e < w.
+            const int lo = x0 - xs, hi = c.w - xs;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const uint32_t keep = (2 * i + 1 < valid ? 0xFFFF0000u : 0u) |
-                                      (2 * i < valid ? 0x0000FFFFu : 0u);
+                const uint32_t keep = (2 * i >= lo && 2 * i < hi ? 0x0000FFFFu : 0u) |
+                                      (2 * i + 1 >= lo && 2 * i + 1 < hi ? 0xFFFF0000u : 0u);
                 q[i] &= keep;
             }
         }
