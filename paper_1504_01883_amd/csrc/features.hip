@@ -112,6 +112,7 @@ struct MedianScratch {
     uint32_t hist[256];
     int32_t bin;
     uint32_t rank;
+    uint32_t est[kWaves];  // the waves' median estimates
 };
 
 // On wave 0: find the bin of a 256-bin LDS histogram that holds 0-based rank
@@ -344,19 +345,23 @@ __device__ __forceinline__ u32x4 depth_chunk(const CropDesc &c, int y, int x0) {
 
 constexpr int kMedBatch = 8;  // 16-byte chunks in flight per thread
 
+// Width (mm) of the median pass's 1 mm window histogram, centred on the
+// estimate.
+constexpr uint32_t kMedWin = 64;
+
 // One u16 pair of the median pass: per-half counts of v >= lo (ge2) and of
-// v != 0 (nz2), and the 1 mm window histogram of [lo, lo + 256). one2 holds
-// 0x10001 (kept opaque to the compiler, see crop_median_fast).
+// v != 0 (nz2), and the 1 mm window histogram of [lo, lo + kMedWin). one2
+// holds 0x10001 (kept opaque to the compiler, see crop_median_fast).
 __device__ __forceinline__ void median_count(uint32_t q, uint32_t lolo, uint32_t lm1,
                                              uint32_t one2, uint32_t &ge2, uint32_t &nz2,
                                              MedianScratch &ms) {
     // v >= lo iff v - (lo - 1) saturates above 0 (lo >= 1, so 0 is not).
     ge2 += pk_min(pk_sub_sat(q, lm1), one2);
     nz2 += pk_min(q, one2);
-    const uint32_t t = pk_sub(q, lolo);  // v - lo; >= 256 for v = 0
+    const uint32_t t = pk_sub(q, lolo);  // v - lo; >= kMedWin for v = 0
     const uint32_t t0 = t & 0xFFFFu, t1 = t >> 16;
-    if (t0 < 256u) atomicAdd(&ms.hist[t0], 1u);
-    if (t1 < 256u) atomicAdd(&ms.hist[t1], 1u);
+    if (t0 < kMedWin) atomicAdd(&ms.hist[t0], 1u);
+    if (t1 < kMedWin) atomicAdd(&ms.hist[t1], 1u);
 }
 
 // End of the median pass for a block of kNW waves: totals over the block,
@@ -441,15 +446,22 @@ __device__ __forceinline__ int32_t crop_median_fast(const CropDesc &c, MedianScr
 #pragma unroll
     for (int u = 0; u < kMedBatch; ++u)
         if (nk > 0) buf[u] = depth_chunk(c, ry0 + min(u, nk - 1) * rows_par, x0);
+    // select_bin scans all 256 bins; the pass fills the first kMedWin.
     for (int i = tid; i < 256; i += kThreads) ms.hist[i] = 0;
-    if (wave == 0) {
-        const int sy = ((2 * (lane >> 3) + 1) * c.h) >> 4;
-        const int sx = ((2 * (lane & 7) + 1) * c.w) >> 4;
-        const uint32_t est = median_estimate(c.depth[(size_t)sy * c.depth_pitch + sx]);
-        if (lane == 0) ms.rank = est;
+    {
+        // Wave w samples grid rows w, w + 4, ... of a 16 x 16 grid over the
+        // crop, so each wave's estimate covers the whole crop.
+        const int gr = 4 * (lane >> 4) + wave, gc = lane & 15;
+        const int sy = ((2 * gr + 1) * c.h) >> 5, sx = ((2 * gc + 1) * c.w) >> 5;
+        const uint32_t e = median_estimate(c.depth[(size_t)sy * c.depth_pitch + sx]);
+        if (lane == 0) ms.est[wave] = e;
     }
     __syncthreads();
-    const int32_t lo = min(max((int32_t)ms.rank - 128, 1), 65536 - 256);
+    // The mean of the middle two of the four wave estimates.
+    const uint32_t ea = min(ms.est[0], ms.est[1]), eb = max(ms.est[0], ms.est[1]);
+    const uint32_t ec = min(ms.est[2], ms.est[3]), ed = max(ms.est[2], ms.est[3]);
+    const int32_t est = (int32_t)((max(ea, ec) + min(eb, ed)) >> 1);
+    const int32_t lo = min(max(est - (int32_t)kMedWin / 2, 1), 65536 - (int32_t)kMedWin);
     const uint32_t lolo = (uint32_t)lo * 0x10001u;
     const uint32_t lm1 = (uint32_t)(lo - 1) * 0x10001u;
     // A 1 in each half that the compiler cannot see: with a visible constant
@@ -811,7 +823,7 @@ __global__ __launch_bounds__(kThreads) void k_features_fast(const CropDesc *__re
 // last workgroup to finish resets both, so the kernel can be relaunched (or
 // replayed from a graph) with no memset in between.
 template <int kPF>
-__global__ __launch_bounds__(kThreads) void k_features_persistent(
+__global__ __launch_bounds__(kThreads, 4) void k_features_persistent(
     const CropDesc *__restrict__ crops, const int32_t *__restrict__ order, int32_t n,
     FeatParams fp, const uint8_t *__restrict__ tables, float *__restrict__ hist,
     uint32_t *__restrict__ counts, uint32_t *__restrict__ queue) {
