@@ -290,6 +290,44 @@ lbpf_status lbpf_graph_create(lbpf_ctx *ctx, const lbpf_batch *batch,
 lbpf_status lbpf_graph_launch(lbpf_graph *graph, void *stream);
 void lbpf_graph_destroy(lbpf_graph *graph);
 
+/* A serving step captured once as a HIP graph and replayed per batch (Sec. 3:
+ * each frame's faces are detected, their features extracted and classified;
+ * here for a batch of frames from many cameras at once). One replay copies
+ * the batch's box table from the pipeline's pinned staging to the device,
+ * runs the fused feature kernel (persistent, largest crop first), the scoring
+ * of weights' precision (quantisation, GEMM, argmax) and copies the
+ * identities back to host memory; every kernel reads the batch's box count
+ * from device memory, so one graph serves batches of 0 .. max_boxes boxes.
+ * Outputs are caller-owned: hist DEVICE [max_boxes][D] FP32, scores_opt
+ * DEVICE [max_boxes][K] FP32 or NULL (then the pipeline keeps its own),
+ * argmax DEVICE [max_boxes] int32, argmax_host_opt HOST [max_boxes] int32 in
+ * pinned memory (hipHostMalloc or a pinned torch tensor) or NULL. Rows past
+ * a batch's size are left unspecified. Requires the default feature
+ * configuration (uniform-59, both channels, window 1..255) and, for FP32
+ * weights, D % 32 == 0 and a 16-byte aligned hist. Allocates its staging and
+ * scratch (charged to the context's budget). The weights must outlive the
+ * pipeline. Errors: LBPF_E_INVALID, LBPF_E_BUDGET (max_boxes outside
+ * 1..LBPF_MAX_BOXES_PER_CALL, budget), LBPF_E_UNSUPPORTED, LBPF_E_HIP. */
+typedef struct lbpf_pipeline lbpf_pipeline;
+lbpf_status lbpf_pipeline_create(lbpf_ctx *ctx, const lbpf_weights *weights, int32_t max_boxes,
+                                 float *hist, float *scores_opt, int32_t *argmax,
+                                 int32_t *argmax_host_opt, lbpf_pipeline **out);
+
+/* Queue one batch on `stream`: the boxes (HOST array, validated like
+ * lbpf_features, then written into the pinned staging in largest-first
+ * order) over the images (HOST array of DEVICE planes, which must stay
+ * valid until the replay has run), then one graph replay. Results
+ * (hist[0 .. n_boxes), scores, argmax, argmax_host) are complete once
+ * `stream` has passed this call. Launches on one pipeline must not overlap:
+ * a launch first waits (on the host) for the previous one's replay to
+ * finish. Errors: LBPF_E_INVALID (as lbpf_features), LBPF_E_BUDGET (more
+ * than max_boxes boxes), LBPF_E_HIP. */
+lbpf_status lbpf_pipeline_launch(lbpf_pipeline *pipeline, const lbpf_image *images,
+                                 int32_t n_images, const lbpf_box *boxes, int32_t n_boxes,
+                                 void *stream);
+int32_t lbpf_pipeline_max_boxes(const lbpf_pipeline *pipeline);
+void lbpf_pipeline_destroy(lbpf_pipeline *pipeline);
+
 /* Enrol K identities: W DEVICE [K][D] FP32 row-major, b DEVICE [K] FP32.
  * The library copies them (and, for BF16/FP16/FP8, quantises them) into a
  * weights object it owns; the caller's buffers may be freed once `stream`

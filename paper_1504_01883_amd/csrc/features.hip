@@ -826,8 +826,10 @@ template <int kPF>
 __global__ __launch_bounds__(kThreads, 4) void k_features_persistent(
     const CropDesc *__restrict__ crops, const int32_t *__restrict__ order, int32_t n,
     FeatParams fp, const uint8_t *__restrict__ tables, float *__restrict__ hist,
-    uint32_t *__restrict__ counts, uint32_t *__restrict__ queue) {
+    uint32_t *__restrict__ counts, uint32_t *__restrict__ queue,
+    const int32_t *__restrict__ n_dev) {
     __shared__ FastShared sh;
+    if (n_dev) n = *n_dev;  // a batch count kept in device memory (graph replays)
     load_tables(sh, tables);
     if (threadIdx.x == 0) sh.next = (int32_t)atomicAdd(&queue[0], 1u);
     __syncthreads();
@@ -934,7 +936,7 @@ bool fast_path_ok(const FeatParams &fp) {
 hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &fp,
                            const uint8_t *d_tables, float *hist, uint32_t *counts,
                            hipStream_t s, const LaunchCfg &lc, const int32_t *order,
-                           uint32_t *queue, int32_t num_cus) {
+                           uint32_t *queue, int32_t num_cus, const int32_t *n_dev) {
     if (n <= 0) return hipSuccess;
     if (fast_path_ok(fp)) {
         const int pf = lc.row_prefetch <= 2 ? 2 : (lc.row_prefetch <= 4 ? 4 : 8);
@@ -943,12 +945,13 @@ hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &f
             const int32_t *ord = lc.sorted ? order : nullptr;
             auto go = [&](auto kern) {
                 hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, crops, ord, n, fp,
-                                   d_tables, hist, counts, queue);
+                                   d_tables, hist, counts, queue, n_dev);
             };
             if (pf == 2) go(k_features_persistent<2>);
             else if (pf == 4) go(k_features_persistent<4>);
             else go(k_features_persistent<8>);
         } else {
+            if (n_dev) return hipErrorInvalidValue;  // device counts: the persistent kernel only
             auto go = [&](auto kern) {
                 hipLaunchKernelGGL(kern, dim3(n), dim3(kThreads), 0, s, crops, fp, d_tables, hist,
                                    counts);
@@ -959,6 +962,7 @@ hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &f
         }
         return hipGetLastError();
     }
+    if (n_dev) return hipErrorInvalidValue;  // device counts: the fast configuration only
     const size_t shmem = (size_t)fp.dim * sizeof(uint32_t);
     // Above 64 KiB of dynamic LDS (the 256-bin mapping) the kernel must opt in.
     static size_t shmem_limit = 64 * 1024;

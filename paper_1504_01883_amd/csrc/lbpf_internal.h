@@ -60,7 +60,7 @@ hipError_t launch_features(const CropDesc *crops, int32_t n, const FeatParams &f
                            const uint8_t *d_tables, float *hist, uint32_t *counts,
                            hipStream_t s, const LaunchCfg &lc = LaunchCfg(),
                            const int32_t *order = nullptr, uint32_t *queue = nullptr,
-                           int32_t num_cus = 256);
+                           int32_t num_cus = 256, const int32_t *n_dev = nullptr);
 hipError_t launch_debug_codes(const CropDesc *crop, const FeatParams &fp, uint8_t *gcodes,
                               uint8_t *dcodes, uint8_t *mask, int32_t w, int32_t h,
                               hipStream_t s);
@@ -75,8 +75,11 @@ hipError_t launch_plain_score(const float *x, const float *W, const float *b, in
 // Reduced-precision scoring (score_lp.hip). Quantised rows have a pitch of
 // lp_pitch(D, mode) bytes (a multiple of 128, zero padded).
 int32_t lp_pitch(int32_t D, int32_t mode);
+// n_dev (launchers below too): when not null, the kernels read the row count
+// from this device word (at most the host count, which sizes the grid), so a
+// captured graph serves batches of any size up to it.
 hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mode, uint8_t *out,
-                             float *scales, hipStream_t s);
+                             float *scales, hipStream_t s, const int32_t *n_dev = nullptr);
 // S: [N][K] scores, or null for argmax only; argmax: [N] or null. scratch
 // (scratch_elems floats) holds the per-tile argmax pairs, or the scores when
 // S is null and the pairs do not fit; it must hold N * K floats when S is
@@ -84,7 +87,7 @@ hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mo
 hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const uint8_t *Wq,
                            const float *sw, const float *b, int32_t K, int32_t D, int32_t mode,
                            float *S, int32_t *argmax, float *scratch, size_t scratch_elems,
-                           hipStream_t s);
+                           hipStream_t s, const int32_t *n_dev = nullptr);
 
 // Warped crops (warp.hip): each crop is sampled from its planes through two
 // 16.16 fixed-point affine frames into a staging crop of pitch w, which the
@@ -133,7 +136,9 @@ int32_t score_f32_splits(int32_t N, int32_t K, int32_t D, int32_t num_cus, size_
 // S is always written; argmax (may be null) gets each row's best identity.
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b,
                             int32_t K, int32_t D, float *S, int32_t *argmax, hipStream_t s,
-                            int32_t splits = 0, float *part = nullptr);
-hipError_t launch_argmax(const float *S, int32_t N, int32_t K, int32_t *argmax, hipStream_t s);
+                            int32_t splits = 0, float *part = nullptr,
+                            const int32_t *n_dev = nullptr);
+hipError_t launch_argmax(const float *S, int32_t N, int32_t K, int32_t *argmax, hipStream_t s,
+                         const int32_t *n_dev = nullptr);
 
 }  // namespace lbpf

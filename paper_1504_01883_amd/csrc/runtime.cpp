@@ -81,6 +81,31 @@ struct lbpf_graph {
     hipGraphExec_t exec = nullptr;
 };
 
+// A captured serving step (lbpf_pipeline_*): per replay the host-written box
+// table is copied up, then features, (quantisation,) scores and argmax run
+// with the batch size read from device memory, and the identities are copied
+// back to the caller's pinned memory.
+struct lbpf_pipeline {
+    lbpf_ctx *ctx = nullptr;
+    const lbpf_weights *w = nullptr;
+    int32_t max_boxes = 0;
+    uint8_t *h_stage = nullptr;  // pinned: CropDesc[max] | int32 order[max] | int32 n
+    uint8_t *d_stage = nullptr;  // the same, on the device
+    size_t stage_bytes = 0, off_order = 0, off_n = 0;
+    uint32_t *d_queue = nullptr;  // persistent feature kernel's work queue
+    float *d_scores = nullptr;    // scores when the caller passes none
+    uint8_t *d_xq = nullptr;      // reduced precision: quantised rows, scales,
+    float *d_sx = nullptr;        //   per-tile argmax pairs
+    float *d_apart = nullptr;
+    size_t apart_elems = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // end of the last replay (its staging may be reused)
+    size_t bytes = 0;           // device bytes charged to the context
+    std::vector<CropDesc> crops;
+    std::vector<int32_t> order;
+};
+
 struct lbpf_weights {
     lbpf_ctx *ctx = nullptr;
     int32_t K = 0, D = 0;
@@ -629,6 +654,145 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
     if (order) HIP_TRY(hipEventRecord(ctx->scratch_ev, s), "hipEventRecord");
     return LBPF_OK;
 }
+
+void lbpf_pipeline_destroy(lbpf_pipeline *p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    for (void *d : {(void *)p->d_stage, (void *)p->d_queue, (void *)p->d_scores, (void *)p->d_xq,
+                    (void *)p->d_sx, (void *)p->d_apart})
+        if (d) (void)hipFree(d);
+    if (p->ctx) p->ctx->used -= p->bytes;
+    delete p;
+}
+
+lbpf_status lbpf_pipeline_create(lbpf_ctx *ctx, const lbpf_weights *w, int32_t max_boxes,
+                                 float *hist, float *scores_opt, int32_t *argmax,
+                                 int32_t *argmax_host_opt, lbpf_pipeline **out) {
+    if (!ctx || !w || !hist || !argmax || !out) return fail(LBPF_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (w->ctx != ctx) return fail(LBPF_E_INVALID, "weights belong to another context");
+    if (max_boxes < 1 || max_boxes > LBPF_MAX_BOXES_PER_CALL)
+        return fail(LBPF_E_BUDGET, "max_boxes outside 1..LBPF_MAX_BOXES_PER_CALL");
+    if (!fast_path_ok(ctx->fp))
+        return fail(LBPF_E_UNSUPPORTED, "pipelines need the default feature configuration "
+                                        "(uniform-59 bins, both channels, window 1..255)");
+    const int32_t K = w->K, D = w->D;
+    const bool lp = w->prec != LBPF_FP32;
+    if (!lp && (D % 32 != 0 || ((uintptr_t)hist & 15) || ((uintptr_t)w->W & 15)))
+        return fail(LBPF_E_UNSUPPORTED, "FP32 pipelines need D % 32 == 0 and 16-byte aligned hist");
+    lbpf_pipeline *p = new (std::nothrow) lbpf_pipeline();
+    if (!p) return fail(LBPF_E_BUDGET, "out of host memory");
+    p->ctx = ctx;
+    p->w = w;
+    p->max_boxes = max_boxes;
+    const size_t mb = (size_t)max_boxes;
+    p->off_order = sizeof(CropDesc) * mb;
+    p->off_n = p->off_order + sizeof(int32_t) * mb;
+    p->stage_bytes = p->off_n + sizeof(int32_t);
+    const int32_t KT = (K + 255) / 256;
+    p->apart_elems = lp ? 2 * mb * (size_t)KT : 0;
+    const size_t need = p->stage_bytes + 2 * sizeof(uint32_t) +
+                        (scores_opt ? 0 : sizeof(float) * mb * (size_t)K) +
+                        (lp ? mb * (size_t)lp_pitch(D, w->prec) + sizeof(float) * mb +
+                                  sizeof(float) * p->apart_elems
+                            : 0);
+    if (!charge(ctx, need)) {
+        delete p;
+        return fail(LBPF_E_BUDGET, "pipeline exceeds the HBM budget");
+    }
+    p->bytes = need;
+    p->crops.reserve(mb);
+    p->order.resize(mb);
+    auto cleanup = [&](lbpf_status st) {
+        lbpf_pipeline_destroy(p);
+        return st;
+    };
+    hipError_t e = hipHostMalloc((void **)&p->h_stage, p->stage_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_stage, p->stage_bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_queue, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(p->d_queue, 0, 2 * sizeof(uint32_t));
+    if (e == hipSuccess && !scores_opt)
+        e = hipMalloc((void **)&p->d_scores, sizeof(float) * mb * (size_t)K);
+    if (e == hipSuccess && lp) e = hipMalloc((void **)&p->d_xq, mb * (size_t)lp_pitch(D, w->prec));
+    if (e == hipSuccess && lp) e = hipMalloc((void **)&p->d_sx, sizeof(float) * mb);
+    if (e == hipSuccess && lp) e = hipMalloc((void **)&p->d_apart, sizeof(float) * p->apart_elems);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "pipeline allocation"));
+    std::memset(p->h_stage, 0, p->stage_bytes);  // n = 0 until the first launch
+
+    float *S = scores_opt ? scores_opt : p->d_scores;
+    const CropDesc *d_crops = reinterpret_cast<const CropDesc *>(p->d_stage);
+    const int32_t *d_order = reinterpret_cast<const int32_t *>(p->d_stage + p->off_order);
+    const int32_t *d_n = reinterpret_cast<const int32_t *>(p->d_stage + p->off_n);
+    // The persistent feature kernel (4 workgroups per CU, 2 rows prefetched)
+    // takes the crops in the order the host wrote: largest first.
+    LaunchCfg lc;
+    lc.persistent = 1;
+    lc.wg_per_cu = 4;
+    lc.row_prefetch = 2;
+    lc.sorted = 1;
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "hipStreamCreate"));
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t el = hipMemcpyAsync(p->d_stage, p->h_stage, p->stage_bytes,
+                                       hipMemcpyHostToDevice, cs);
+        if (el == hipSuccess)
+            el = launch_features(d_crops, max_boxes, ctx->fp, ctx->d_bins, hist, nullptr, cs, lc,
+                                 d_order, p->d_queue, ctx->num_cus, d_n);
+        if (el == hipSuccess && !lp)
+            el = launch_score_f32(hist, max_boxes, w->W, w->b, K, D, S, argmax, cs, 1, nullptr, d_n);
+        if (el == hipSuccess && lp)
+            el = launch_quant_rows(hist, max_boxes, D, w->prec, p->d_xq, p->d_sx, cs, d_n);
+        if (el == hipSuccess && lp)
+            el = launch_score_lp(p->d_xq, p->d_sx, max_boxes, w->Wq, w->sw, w->b, K, D, w->prec, S,
+                                 argmax, p->d_apart, p->apart_elems, cs, d_n);
+        if (el == hipSuccess && argmax_host_opt)
+            el = hipMemcpyAsync(argmax_host_opt, argmax, sizeof(int32_t) * mb,
+                                hipMemcpyDeviceToHost, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        p->graph = graph;
+        e = el != hipSuccess ? el : ee;
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "pipeline capture"));
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "hipGraphInstantiate"));
+    *out = p;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_pipeline_launch(lbpf_pipeline *p, const lbpf_image *images, int32_t n_images,
+                                 const lbpf_box *boxes, int32_t n_boxes, void *stream) {
+    if (!p) return fail(LBPF_E_INVALID, "pipeline is NULL");
+    if (n_boxes > p->max_boxes) return fail(LBPF_E_BUDGET, "more boxes than the pipeline's max_boxes");
+    lbpf_status st = resolve(p->ctx, images, n_images, boxes, n_boxes, p->crops);
+    if (st != LBPF_OK) return st;
+    // The previous replay reads the staging buffer: wait for it to finish
+    // (a no-op when the caller already waited for its results).
+    HIP_TRY(hipEventSynchronize(p->done), "hipEventSynchronize");
+    const size_t n = (size_t)n_boxes;
+    for (size_t i = 0; i < n; ++i) p->order[i] = (int32_t)i;
+    std::stable_sort(p->order.begin(), p->order.begin() + n, [&](int32_t a, int32_t c) {
+        return (int64_t)p->crops[a].w * p->crops[a].h > (int64_t)p->crops[c].w * p->crops[c].h;
+    });
+    std::memcpy(p->h_stage, p->crops.data(), sizeof(CropDesc) * n);
+    std::memcpy(p->h_stage + p->off_order, p->order.data(), sizeof(int32_t) * n);
+    const int32_t nb = n_boxes;
+    std::memcpy(p->h_stage + p->off_n, &nb, sizeof nb);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipGraphLaunch(p->exec, s), "hipGraphLaunch");
+    HIP_TRY(hipEventRecord(p->done, s), "hipEventRecord");
+    return LBPF_OK;
+}
+
+int32_t lbpf_pipeline_max_boxes(const lbpf_pipeline *p) { return p ? p->max_boxes : -1; }
 
 size_t lbpf_warp_crop_bytes(int32_t w, int32_t h) {
     if (w < 3 || h < 3 || w > LBPF_MAX_SIDE || h > LBPF_MAX_SIDE) return 0;

@@ -139,8 +139,10 @@ __global__ __launch_bounds__(512) void k_score_f32(const float *__restrict__ X, 
 // (lowest k) maximum, then a butterfly picks the larger value, or the lower
 // index on equal values.
 __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ S, int32_t N, int32_t K,
-                                                int32_t *__restrict__ out) {
+                                                int32_t *__restrict__ out,
+                                                const int32_t *__restrict__ n_dev) {
     const int lane = threadIdx.x & 63;
+    if (n_dev) N = *n_dev;
     const int32_t n = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (n >= N) return;
     const float *row = S + (size_t)n * K;
@@ -221,7 +223,7 @@ template <int kRingN, int kTK>
 __global__ __launch_bounds__(256) void k_score_f32_split(
     const float *__restrict__ X, int32_t N, const float *__restrict__ W,
     const float *__restrict__ bias, int32_t K, int32_t D, float *__restrict__ S, int32_t splits,
-    float *__restrict__ part) {
+    float *__restrict__ part, const int32_t *__restrict__ n_dev) {
     // Tile: 128 feature rows x kTK identities (kTK = 128 or 64); wave w owns
     // rows 64 (w & 1) .. +64 and identities (kTK / 2) (w >> 1) .. + kTK / 2 as
     // 2 x kJB blocks of 32 x 32.
@@ -234,6 +236,8 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int32_t n0 = blockIdx.x * kTM, k0 = blockIdx.y * kTK, sp = blockIdx.z;
+    if (n_dev) N = *n_dev;  // the grid covers the most rows; tiles past N leave
+    if (n0 >= N) return;    // uniform
     const int32_t dsp = D / splits, d0 = sp * dsp;
     const int nst = dsp / (kSlice / 4);
     auto swz = [](int row, int chunk) { return chunk ^ (row & 7); };
@@ -440,13 +444,13 @@ int32_t score_f32_splits(int32_t N, int32_t K, int32_t D, int32_t num_cus, size_
 
 hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const float *b, int32_t K,
                             int32_t D, float *S, int32_t *argmax, hipStream_t s, int32_t splits,
-                            float *part) {
+                            float *part, const int32_t *n_dev) {
     if (N <= 0 || K <= 0) return hipSuccess;
     const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
     if (aligned && splits >= 1 && D % (32 * splits) == 0 && (splits == 1 || part)) {
         dim3 g((N + 127) / 128, (K + kSplitTK - 1) / kSplitTK, splits);
         hipLaunchKernelGGL((k_score_f32_split<4, kSplitTK>), g, dim3(256), 0, s, X, N, W, b, K, D,
-                           S, splits, part);
+                           S, splits, part, n_dev);
         if (splits > 1) {
             const bool v4 = K % 4 == 0 && ((uintptr_t)S % 16 == 0) && ((uintptr_t)b % 16 == 0);
             if (v4)
@@ -459,8 +463,9 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !argmax) return e;
-        return launch_argmax(S, N, K, argmax, s);
+        return launch_argmax(S, N, K, argmax, s, n_dev);
     }
+    if (n_dev) return hipErrorInvalidValue;  // device row counts: the tiled kernel only
     dim3 grid((N + kTile - 1) / kTile, (K + kTile - 1) / kTile);
     const bool vec = (D % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
     if (vec)
@@ -472,9 +477,10 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
     return launch_argmax(S, N, K, argmax, s);
 }
 
-hipError_t launch_argmax(const float *S, int32_t N, int32_t K, int32_t *argmax, hipStream_t s) {
+hipError_t launch_argmax(const float *S, int32_t N, int32_t K, int32_t *argmax, hipStream_t s,
+                         const int32_t *n_dev) {
     if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_argmax, dim3((N + 3) / 4), dim3(256), 0, s, S, N, K, argmax);
+    hipLaunchKernelGGL(k_argmax, dim3((N + 3) / 4), dim3(256), 0, s, S, N, K, argmax, n_dev);
     return hipGetLastError();
 }
 

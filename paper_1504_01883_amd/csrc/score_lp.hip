@@ -112,9 +112,11 @@ template <int kMode>
 __global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ X, int32_t rows,
                                                     int32_t D, int32_t pitch,
                                                     uint8_t *__restrict__ out,
-                                                    float *__restrict__ scales) {
+                                                    float *__restrict__ scales,
+                                                    const int32_t *__restrict__ n_dev) {
     __shared__ float part[4];
     const int r = blockIdx.x;
+    if (n_dev && r >= *n_dev) return;  // uniform: fewer rows than the grid
     const float *x = X + (size_t)r * D;
     float amax = 0.0f;
     for (int i = threadIdx.x; i < D; i += 256) amax = fmaxf(amax, fabsf(x[i]));
@@ -152,10 +154,11 @@ template <int kMode, int kC>
 __global__ __launch_bounds__(256) void k_quant_rows_vec(const float *__restrict__ X, int32_t rows,
                                                         int32_t D, int32_t pitch,
                                                         uint8_t *__restrict__ out,
-                                                        float *__restrict__ scales) {
+                                                        float *__restrict__ scales,
+                                                        const int32_t *__restrict__ n_dev) {
     const int lane = threadIdx.x & 63;
     const int32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= rows) return;
+    if (r >= (n_dev ? *n_dev : rows)) return;
     const int nq = D >> 2;
     const f32x4 *x = reinterpret_cast<const f32x4 *>(X + (size_t)r * D);
     f32x4 v[kC];
@@ -242,8 +245,10 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
                                                   const uint8_t *__restrict__ Wq,
                                                   const float *__restrict__ sw,
                                                   const float *__restrict__ bias, int32_t K,
-                                                  int32_t pitch, float *__restrict__ S) {
+                                                  int32_t pitch, float *__restrict__ S,
+                                                  const int32_t *__restrict__ n_dev) {
     __shared__ __attribute__((aligned(16))) uint8_t sA[kTM * kPitch];
+    if (n_dev) N = *n_dev;  // the grid covers the most rows; tiles past N leave
     __shared__ __attribute__((aligned(16))) uint8_t sB[kTN * kPitch];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -255,6 +260,7 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
     const uint32_t xcd = pid & 7u, per = nwg >> 3, rem = nwg & 7u;
     const uint32_t L = xcd * per + min(xcd, rem) + (pid >> 3);
     const uint32_t KT = (uint32_t)(K + kTN - 1) / kTN, NT = (uint32_t)(N + kTM - 1) / kTM;
+    if (L >= NT * KT) return;  // uniform
     const uint32_t g = L / (kGroupN * KT), i_g = L - g * (kGroupN * KT);
     const uint32_t gn = min((uint32_t)kGroupN, NT - g * kGroupN);
     const int32_t n0 = (int32_t)(g * kGroupN + i_g % gn) * kTM;
@@ -448,7 +454,9 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
                                                           const float *__restrict__ bias,
                                                           int32_t K, int32_t pitch,
                                                           float *__restrict__ S,
-                                                          float *__restrict__ apart) {
+                                                          float *__restrict__ apart,
+                                                          const int32_t *__restrict__ n_dev) {
+    if (n_dev) N = *n_dev;  // the grid covers the most rows; tiles past N leave
     constexpr int kCW = kBigT / (kW / 2);  // identities per wave
     constexpr int kJB = kCW / 32;          // 32-wide blocks per wave
     constexpr int kCopies = 2 * (kBigT / kW / 16);
@@ -461,6 +469,7 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
     const uint32_t xcd = pid & 7u, per = nwg >> 3, rem = nwg & 7u;
     const uint32_t L = xcd * per + min(xcd, rem) + (pid >> 3);
     const uint32_t KT = (uint32_t)(K + kBigT - 1) / kBigT, NT = (uint32_t)(N + kBigT - 1) / kBigT;
+    if (L >= NT * KT) return;  // uniform
     const uint32_t g = L / (kGroupN * KT), i_g = L - g * (kGroupN * KT);
     const uint32_t gn = min((uint32_t)kGroupN, NT - g * kGroupN);
     const int32_t n0 = (int32_t)(g * kGroupN + i_g % gn) * kBigT;
@@ -675,7 +684,9 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
 // thread per row: tiles in increasing identity order, a strict > keeps the
 // lowest identity among equal scores.
 __global__ __launch_bounds__(256) void k_argmax_tiles(const float *__restrict__ apart, int32_t N,
-                                                      int32_t KT, int32_t *__restrict__ out) {
+                                                      int32_t KT, int32_t *__restrict__ out,
+                                                      const int32_t *__restrict__ n_dev) {
+    if (n_dev) N = *n_dev;
     const int32_t n = blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
     const float *pv = apart + (size_t)n * KT;
@@ -704,38 +715,38 @@ int32_t lp_pitch(int32_t D, int32_t mode) {
 }
 
 hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mode, uint8_t *out,
-                             float *scales, hipStream_t s) {
+                             float *scales, hipStream_t s, const int32_t *n_dev) {
     if (rows <= 0) return hipSuccess;
     const int32_t pitch = lp_pitch(D, mode);
     if (D % 4 == 0 && D <= 256 * kQuantChunks && ((uintptr_t)X & 15) == 0) {
         const dim3 grid((rows + 3) / 4);
         if (mode == LBPF_BF16)
             hipLaunchKernelGGL((k_quant_rows_vec<LBPF_BF16, kQuantChunks>), grid, dim3(256), 0, s,
-                               X, rows, D, pitch, out, scales);
+                               X, rows, D, pitch, out, scales, n_dev);
         else if (mode == LBPF_FP16)
             hipLaunchKernelGGL((k_quant_rows_vec<LBPF_FP16, kQuantChunks>), grid, dim3(256), 0, s,
-                               X, rows, D, pitch, out, scales);
+                               X, rows, D, pitch, out, scales, n_dev);
         else
             hipLaunchKernelGGL((k_quant_rows_vec<LBPF_FP8_E4M3, kQuantChunks>), grid, dim3(256), 0,
-                               s, X, rows, D, pitch, out, scales);
+                               s, X, rows, D, pitch, out, scales, n_dev);
         return hipGetLastError();
     }
     if (mode == LBPF_BF16)
         hipLaunchKernelGGL(k_quant_rows<LBPF_BF16>, dim3(rows), dim3(256), 0, s, X, rows, D, pitch,
-                           out, scales);
+                           out, scales, n_dev);
     else if (mode == LBPF_FP16)
         hipLaunchKernelGGL(k_quant_rows<LBPF_FP16>, dim3(rows), dim3(256), 0, s, X, rows, D, pitch,
-                           out, scales);
+                           out, scales, n_dev);
     else
         hipLaunchKernelGGL(k_quant_rows<LBPF_FP8_E4M3>, dim3(rows), dim3(256), 0, s, X, rows, D,
-                           pitch, out, scales);
+                           pitch, out, scales, n_dev);
     return hipGetLastError();
 }
 
 hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const uint8_t *Wq,
                            const float *sw, const float *b, int32_t K, int32_t D, int32_t mode,
                            float *S, int32_t *argmax, float *scratch, size_t scratch_elems,
-                           hipStream_t s) {
+                           hipStream_t s, const int32_t *n_dev) {
     if (N <= 0 || K <= 0) return hipSuccess;
     const int32_t pitch = lp_pitch(D, mode);
     if (N >= 2 * kBigT && K >= kBigT) {
@@ -750,34 +761,34 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
         constexpr int kW = kBigWaves;
         if (mode == LBPF_BF16)
             hipLaunchKernelGGL((k_score_lp_big<LBPF_BF16, kW>), grid, dim3(64 * kW), 0, s, Xq, sx,
-                               N, Wq, sw, b, K, pitch, Sout, apart);
+                               N, Wq, sw, b, K, pitch, Sout, apart, n_dev);
         else if (mode == LBPF_FP16)
             hipLaunchKernelGGL((k_score_lp_big<LBPF_FP16, kW>), grid, dim3(64 * kW), 0, s, Xq, sx,
-                               N, Wq, sw, b, K, pitch, Sout, apart);
+                               N, Wq, sw, b, K, pitch, Sout, apart, n_dev);
         else
             hipLaunchKernelGGL((k_score_lp_big<LBPF_FP8_E4M3, kW>), grid, dim3(64 * kW), 0, s, Xq,
-                               sx, N, Wq, sw, b, K, pitch, Sout, apart);
+                               sx, N, Wq, sw, b, K, pitch, Sout, apart, n_dev);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !argmax) return e;
-        if (!fuse) return launch_argmax(Sout, N, K, argmax, s);
+        if (!fuse) return launch_argmax(Sout, N, K, argmax, s, n_dev);
         hipLaunchKernelGGL(k_argmax_tiles, dim3((N + 255) / 256), dim3(256), 0, s, apart, N, KT,
-                           argmax);
+                           argmax, n_dev);
         return hipGetLastError();
     }
     if (!S) S = scratch;
     dim3 grid(((K + kTN - 1) / kTN) * ((N + kTM - 1) / kTM));
     if (mode == LBPF_BF16)
         hipLaunchKernelGGL(k_score_lp<LBPF_BF16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,
-                           pitch, S);
+                           pitch, S, n_dev);
     else if (mode == LBPF_FP16)
         hipLaunchKernelGGL(k_score_lp<LBPF_FP16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,
-                           pitch, S);
+                           pitch, S, n_dev);
     else
         hipLaunchKernelGGL(k_score_lp<LBPF_FP8_E4M3>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b,
-                           K, pitch, S);
+                           K, pitch, S, n_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !argmax) return e;
-    return launch_argmax(S, N, K, argmax, s);
+    return launch_argmax(S, N, K, argmax, s, n_dev);
 }
 
 }  // namespace lbpf

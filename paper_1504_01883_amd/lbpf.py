@@ -33,7 +33,8 @@ EXPORTS = [
     "lbpf_score_plain", "lbpf_batch_set_launch", "lbpf_batch_get_launch", "lbpf_tune_batch",
     "lbpf_graph_create", "lbpf_graph_launch", "lbpf_graph_destroy", "lbpf_warp_crop_bytes",
     "lbpf_features_warped", "lbpf_train_workspace_bytes", "lbpf_train_ovr", "lbpf_track",
-    "lbpf_score_noalloc",
+    "lbpf_score_noalloc", "lbpf_pipeline_create", "lbpf_pipeline_launch",
+    "lbpf_pipeline_max_boxes", "lbpf_pipeline_destroy",
 ]
 
 
@@ -138,6 +139,10 @@ def load():
                                 ctypes.c_uint64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lbpf_track": (st, [vp, vp, vp, i32, vp, vp, i32, ctypes.c_int64, vp, vp, vp]),
         "lbpf_score_noalloc": (st, [vp, i32, vp, vp, i32, i32, vp, vp, vp]),
+        "lbpf_pipeline_create": (st, [vp, vp, i32, vp, vp, vp, vp, vp]),
+        "lbpf_pipeline_launch": (st, [vp, vp, i32, vp, i32, vp]),
+        "lbpf_pipeline_max_boxes": (i32, [vp]),
+        "lbpf_pipeline_destroy": (None, [vp]),
         "lbpf_status_string": (ctypes.c_char_p, [st]),
         "lbpf_last_error": (ctypes.c_char_p, []),
     }
@@ -277,6 +282,44 @@ class Graph:
     def close(self):
         if self._h:
             load().lbpf_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pipeline:
+    """A captured serving step (lbpf_pipeline): features + scores + argmax of
+    batches of up to max_boxes boxes, one graph replay per batch. Outputs live
+    in tensors the pipeline holds: hist [max, D], scores [max, K], argmax
+    [max] on the device and argmax_host [max] in pinned host memory."""
+
+    def __init__(self, ctx: "Context", weights: Weights, max_boxes: int, device="cuda"):
+        self._keep = (ctx, weights)
+        self.max_boxes = max_boxes
+        self.hist = torch.empty((max_boxes, ctx.dim), dtype=torch.float32, device=device)
+        self.scores = torch.empty((max_boxes, weights.K), dtype=torch.float32, device=device)
+        self.argmax = torch.empty((max_boxes,), dtype=torch.int32, device=device)
+        self.argmax_host = torch.empty((max_boxes,), dtype=torch.int32).pin_memory()
+        h = ctypes.c_void_p()
+        _check(load().lbpf_pipeline_create(ctx._h, weights._h, max_boxes, _dptr(self.hist),
+                                           _dptr(self.scores), _dptr(self.argmax),
+                                           self.argmax_host.data_ptr(), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, images: "ImageTable", boxes):
+        """Queue one batch on the current stream. boxes: [n, 5] (image, x, y,
+        w, h) host rows indexing `images`."""
+        bx, n = make_boxes(boxes)
+        _check(load().lbpf_pipeline_launch(self._h, images.arr, images.n, bx, n, _stream()))
+        return n
+
+    def close(self):
+        if self._h:
+            load().lbpf_pipeline_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -463,6 +506,9 @@ class Context:
 
     def graph(self, batch: Batch, hist, weights=None, scores=None, argmax=None) -> Graph:
         return Graph(self, batch, weights, hist, scores, argmax)
+
+    def pipeline(self, weights: Weights, max_boxes: int) -> Pipeline:
+        return Pipeline(self, weights, max_boxes)
 
     def weights(self, W: torch.Tensor, b: torch.Tensor, precision="fp32") -> Weights:
         return Weights(self, W, b, precision)
