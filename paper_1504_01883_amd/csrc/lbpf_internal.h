@@ -72,14 +72,21 @@ hipError_t launch_plain_features(const CropDesc &c, const FeatParams &fp, const 
 hipError_t launch_plain_score(const float *x, const float *W, const float *b, int32_t K,
                               int32_t D, float *scores, int32_t *argmax, hipStream_t s);
 
-// Reduced-precision scoring (score_lp.hip). Quantised rows have a pitch of
-// lp_pitch(D, mode) bytes (a multiple of 128, zero padded).
+// Reduced-precision scoring (score_lp.hip). Quantised weight rows have a
+// pitch of lp_pitch(D, mode) bytes, feature rows lp_pitch_features(D, mode)
+// (multiples of 128, zero padded; they differ for the split FP16 mode, whose
+// segments are lp_seg(D) bytes).
+int32_t lp_seg(int32_t D);
 int32_t lp_pitch(int32_t D, int32_t mode);
+int32_t lp_pitch_features(int32_t D, int32_t mode);
 // n_dev (launchers below too): when not null, the kernels read the row count
 // from this device word (at most the host count, which sizes the grid), so a
 // captured graph serves batches of any size up to it.
+// weights: quantise weight rows (split FP16: three segments) rather than
+// feature rows.
 hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mode, uint8_t *out,
-                             float *scales, hipStream_t s, const int32_t *n_dev = nullptr);
+                             float *scales, hipStream_t s, const int32_t *n_dev = nullptr,
+                             bool weights = false);
 // S: [N][K] scores, or null for argmax only; argmax: [N] or null. scratch
 // (scratch_elems floats) holds the per-tile argmax pairs, or the scores when
 // S is null and the pairs do not fit; it must hold N * K floats when S is

@@ -526,23 +526,30 @@ lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, i
                                 lbpf_precision precision, lbpf_weights **out, void *stream) {
     if (!ctx || !W || !b || !out || K < 1) return fail(LBPF_E_INVALID, "bad weights arguments");
     *out = nullptr;
-    if (precision < LBPF_FP32 || precision > LBPF_FP8_E4M3)
+    if (precision < LBPF_FP32 || precision > LBPF_F16X3)
         return fail(LBPF_E_UNSUPPORTED, "unknown precision");
     const int32_t D = ctx->fp.dim;
     const bool lp = precision != LBPF_FP32;
     const size_t bbytes = sizeof(float) * (size_t)K;
     const size_t wbytes = lp ? (size_t)K * lp_pitch(D, precision) + bbytes
                              : sizeof(float) * (size_t)K * D;
-    // The first reduced-precision weights also size the context's feature
-    // quantisation scratch (kLpChunkRows rows at the widest pitch). Both of
-    // its buffers are allocated here, before the weights, and kept only as a
-    // pair: on any failure neither stays and the charge is refunded.
-    const size_t xq_need =
-        (lp && (!ctx->d_xq || !ctx->d_sx)) ? (size_t)kLpChunkRows * lp_pitch(D, LBPF_BF16) : 0;
-    const size_t sx_need = xq_need ? sizeof(float) * kLpChunkRows : 0;
+    // Reduced-precision weights need the context's feature quantisation
+    // scratch: kLpChunkRows rows at this precision's feature pitch (at least
+    // the BF16 one). It is allocated with the first such weights and grows
+    // when wider ones arrive (split FP16 rows are twice as wide); its two
+    // buffers are replaced as a pair, and on any failure the old pair stays
+    // and the charge is refunded.
+    const size_t xq_want =
+        lp ? (size_t)kLpChunkRows * (size_t)std::max(lp_pitch_features(D, LBPF_BF16),
+                                                     lp_pitch_features(D, precision))
+           : 0;
+    const bool grow = lp && (!ctx->d_xq || !ctx->d_sx || ctx->xq_bytes < xq_want);
+    const size_t xq_need = grow ? xq_want : 0;
+    const size_t sx_need = grow ? sizeof(float) * kLpChunkRows : 0;
+    const size_t old_pair = (grow && ctx->d_xq) ? ctx->xq_bytes + sizeof(float) * kLpChunkRows : 0;
     if (!charge(ctx, wbytes + bbytes + xq_need + sx_need))
         return fail(LBPF_E_BUDGET, "weights exceed the HBM budget");
-    if (xq_need) {
+    if (grow) {
         uint8_t *xq = nullptr;
         float *sx = nullptr;
         hipError_t ea = hipMalloc((void **)&xq, xq_need);
@@ -551,6 +558,13 @@ lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, i
             if (xq) (void)hipFree(xq);
             ctx->used -= wbytes + bbytes + xq_need + sx_need;
             return fail_hip(ea, "quantisation scratch");
+        }
+        if (ctx->d_xq || ctx->d_sx) {
+            // Scoring already queued may still read the old pair.
+            (void)hipDeviceSynchronize();
+            if (ctx->d_xq) (void)hipFree(ctx->d_xq);
+            if (ctx->d_sx) (void)hipFree(ctx->d_sx);
+            ctx->used -= old_pair;
         }
         ctx->d_xq = xq;
         ctx->d_sx = sx;
@@ -576,7 +590,7 @@ lbpf_status lbpf_weights_create(lbpf_ctx *ctx, const float *W, const float *b, i
     } else {
         if (e == hipSuccess) e = hipMalloc((void **)&w->Wq, (size_t)K * lp_pitch(D, precision));
         if (e == hipSuccess) e = hipMalloc((void **)&w->sw, bbytes);
-        if (e == hipSuccess) e = launch_quant_rows(W, K, D, precision, w->Wq, w->sw, s);
+        if (e == hipSuccess) e = launch_quant_rows(W, K, D, precision, w->Wq, w->sw, s, nullptr, true);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -697,7 +711,7 @@ lbpf_status lbpf_pipeline_create(lbpf_ctx *ctx, const lbpf_weights *w, int32_t m
     p->apart_elems = lp ? 2 * mb * (size_t)KT : 0;
     const size_t need = p->stage_bytes + 2 * sizeof(uint32_t) +
                         (scores_opt ? 0 : sizeof(float) * mb * (size_t)K) +
-                        (lp ? mb * (size_t)lp_pitch(D, w->prec) + sizeof(float) * mb +
+                        (lp ? mb * (size_t)lp_pitch_features(D, w->prec) + sizeof(float) * mb +
                                   sizeof(float) * p->apart_elems
                             : 0);
     if (!charge(ctx, need)) {
@@ -717,7 +731,8 @@ lbpf_status lbpf_pipeline_create(lbpf_ctx *ctx, const lbpf_weights *w, int32_t m
     if (e == hipSuccess) e = hipMemset(p->d_queue, 0, 2 * sizeof(uint32_t));
     if (e == hipSuccess && !scores_opt)
         e = hipMalloc((void **)&p->d_scores, sizeof(float) * mb * (size_t)K);
-    if (e == hipSuccess && lp) e = hipMalloc((void **)&p->d_xq, mb * (size_t)lp_pitch(D, w->prec));
+    if (e == hipSuccess && lp)
+        e = hipMalloc((void **)&p->d_xq, mb * (size_t)lp_pitch_features(D, w->prec));
     if (e == hipSuccess && lp) e = hipMalloc((void **)&p->d_sx, sizeof(float) * mb);
     if (e == hipSuccess && lp) e = hipMalloc((void **)&p->d_apart, sizeof(float) * p->apart_elems);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);

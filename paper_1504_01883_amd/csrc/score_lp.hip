@@ -39,6 +39,14 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Split FP32 operands (LBPF_F16X3): a row scaled by 2^-sh is stored as an
+// FP16 high part h and an FP16 low part l = fp16(x - h), in segments of
+// lp_seg(D) bytes: feature rows as [h | l], weight rows as [h | l | h]. The
+// GEMM walks three segments of the reduction, reading the feature row's h
+// twice (the A operand's segment remap), so one FP16 product sums
+// h_x h_w + h_x l_w + l_x h_w.
+constexpr int kF16X3W = 5;  // quantiser mode of split weight rows
+
 constexpr int kTM = 256, kTN = 128;  // workgroup tile
 constexpr int kRowB = 128;           // bytes of k per stage and row
 constexpr int kPitch = 144;          // LDS row pitch (bytes)
@@ -137,6 +145,22 @@ __global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ X,
         uint16_t *o16 = reinterpret_cast<uint16_t *>(o);
         for (int i = threadIdx.x; i < pitch / 2; i += 256)
             o16[i] = i < D ? to_f16_rne(ldexpf(x[i], -sh)) : 0;
+    } else if (kMode == LBPF_F16X3 || kMode == kF16X3W) {
+        int e = 0;
+        if (amax > 0.0f) frexpf(amax, &e);
+        const int sh = (amax > 0.0f) ? (e - 1) - 14 : 0;
+        if (threadIdx.x == 0) scales[r] = ldexpf(1.0f, sh);
+        uint16_t *o16 = reinterpret_cast<uint16_t *>(o);
+        const int seg = pitch / (kMode == kF16X3W ? 6 : 4);  // elements per segment
+        for (int i = threadIdx.x; i < seg; i += 256) {
+            const float y = i < D ? ldexpf(x[i], -sh) : 0.0f;
+            const _Float16 hv = (_Float16)y;
+            const uint16_t hb = __builtin_bit_cast(uint16_t, hv);
+            const uint16_t lb = to_f16_rne(y - (float)hv);
+            o16[i] = hb;
+            o16[seg + i] = lb;
+            if (kMode == kF16X3W) o16[2 * seg + i] = hb;
+        }
     } else {
         const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
         if (threadIdx.x == 0) scales[r] = s;
@@ -173,6 +197,43 @@ __global__ __launch_bounds__(256) void k_quant_rows_vec(const float *__restrict_
     amax = wave_max(amax);
     uint8_t *o = out + (size_t)r * pitch;
     constexpr int kEB = kMode == LBPF_FP8_E4M3 ? 1 : 2;
+    if constexpr (kMode == LBPF_F16X3 || kMode == kF16X3W) {
+        int e = 0;
+        if (amax > 0.0f) frexpf(amax, &e);
+        const int sh = (amax > 0.0f) ? (e - 1) - 14 : 0;
+        if (lane == 0) scales[r] = ldexpf(1.0f, sh);
+        const int seg = pitch / (kMode == kF16X3W ? 3 : 2);  // bytes per segment
+        // The high part is the scaled value rounded to FP16, the low part
+        // the rounded remainder (exact in FP32: h is within an FP16 ulp).
+        auto split = [&](float f, uint32_t &hb, uint32_t &lb) {
+            const float y = ldexpf(f, -sh);
+            const _Float16 hv = (_Float16)y;
+            hb = __builtin_bit_cast(uint16_t, hv);
+            lb = to_f16_rne(y - (float)hv);
+        };
+#pragma unroll
+        for (int c = 0; c < kC; ++c) {
+            const int q = c * 64 + lane;
+            if (q < nq) {
+                uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
+                split(v[c].x, h0, l0);
+                split(v[c].y, h1, l1);
+                split(v[c].z, h2, l2);
+                split(v[c].w, h3, l3);
+                const uint2 hw = uint2{h0 | (h1 << 16), h2 | (h3 << 16)};
+                *reinterpret_cast<uint2 *>(o + 8 * q) = hw;
+                *reinterpret_cast<uint2 *>(o + seg + 8 * q) = uint2{l0 | (l1 << 16), l2 | (l3 << 16)};
+                if constexpr (kMode == kF16X3W) *reinterpret_cast<uint2 *>(o + 2 * seg + 8 * q) = hw;
+            }
+        }
+        // Zero pad every segment past D (segments are multiples of 128 bytes).
+        for (int q = nq + lane; q < seg / 8; q += 64) {
+            *reinterpret_cast<uint2 *>(o + 8 * q) = uint2{0u, 0u};
+            *reinterpret_cast<uint2 *>(o + seg + 8 * q) = uint2{0u, 0u};
+            if constexpr (kMode == kF16X3W) *reinterpret_cast<uint2 *>(o + 2 * seg + 8 * q) = uint2{0u, 0u};
+        }
+        return;
+    }
     if constexpr (kMode == LBPF_FP8_E4M3) {
         const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
         if (lane == 0) scales[r] = s;
@@ -246,7 +307,8 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
                                                   const float *__restrict__ sw,
                                                   const float *__restrict__ bias, int32_t K,
                                                   int32_t pitch, float *__restrict__ S,
-                                                  const int32_t *__restrict__ n_dev) {
+                                                  const int32_t *__restrict__ n_dev,
+                                                  int32_t a_pitch, int32_t a_seg) {
     __shared__ __attribute__((aligned(16))) uint8_t sA[kTM * kPitch];
     if (n_dev) N = *n_dev;  // the grid covers the most rows; tiles past N leave
     __shared__ __attribute__((aligned(16))) uint8_t sB[kTN * kPitch];
@@ -271,10 +333,13 @@ __global__ __launch_bounds__(256) void k_score_lp(const uint8_t *__restrict__ Xq
     const int ch = tid & 7, r0 = tid >> 3;
     u32x4 ra[8], rb[4];
     auto load_stage = [&](int32_t kb) {
+        // The feature row's byte for reduction byte kb (split operands read
+        // their first segment twice).
+        const int32_t kba = (a_seg && kb >= a_seg) ? kb - a_seg : kb;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int32_t n = n0 + r0 + 32 * j;
-            ra[j] = n < N ? *reinterpret_cast<const u32x4 *>(Xq + (size_t)n * pitch + kb + 16 * ch)
+            ra[j] = n < N ? *reinterpret_cast<const u32x4 *>(Xq + (size_t)n * a_pitch + kba + 16 * ch)
                           : u32x4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
@@ -413,15 +478,18 @@ template <int kW>
 __device__ __forceinline__ void copy_stage(const uint8_t *__restrict__ Xq, int32_t N, int32_t n0,
                                            const uint8_t *__restrict__ Wq, int32_t K, int32_t k0,
                                            int32_t pitch, int32_t kb, uint8_t *buf, int wave,
-                                           int lane) {
+                                           int lane, int32_t a_pitch, int32_t a_seg) {
     constexpr int kPer = kBigT / kW / 16;  // instructions per wave and matrix
     const int r_in = lane >> 2, pos = lane & 3;
+    // The feature row's byte for reduction byte kb (split operands read their
+    // first segment twice; a 64-byte stage never straddles two segments).
+    const int32_t kba = (a_seg && kb >= a_seg) ? kb - a_seg : kb;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int r = (wave * kPer + j) * 16 + r_in;  // 0..255
         const int c = swz(r, pos);
         const int32_t n = min(n0 + r, N - 1);
-        const uint8_t *src = Xq + (size_t)n * pitch + kb + 16 * c;
+        const uint8_t *src = Xq + (size_t)n * a_pitch + kba + 16 * c;
         __builtin_amdgcn_global_load_lds((glb_void_t *)src,
                                          (lds_void_t *)(buf + (wave * kPer + j) * 1024), 16, 0, 0);
     }
@@ -455,7 +523,8 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
                                                           int32_t K, int32_t pitch,
                                                           float *__restrict__ S,
                                                           float *__restrict__ apart,
-                                                          const int32_t *__restrict__ n_dev) {
+                                                          const int32_t *__restrict__ n_dev,
+                                                          int32_t a_pitch, int32_t a_seg) {
     if (n_dev) N = *n_dev;  // the grid covers the most rows; tiles past N leave
     constexpr int kCW = kBigT / (kW / 2);  // identities per wave
     constexpr int kJB = kCW / 32;          // 32-wide blocks per wave
@@ -537,7 +606,7 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
         barrier_lds();
         if (st + kStages < nst)
             copy_stage<kW>(Xq, N, n0, Wq, K, k0, pitch, (st + kStages) * kStageB,
-                           lds + (st % kStages) * kStageBytes, wave, lane);
+                           lds + (st % kStages) * kStageBytes, wave, lane, a_pitch, a_seg);
         read(st + 1, nxt);
         mma(cur);
     };
@@ -545,7 +614,7 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
     for (int st = 0; st < kStages; ++st)
         if (st < nst)
             copy_stage<kW>(Xq, N, n0, Wq, K, k0, pitch, st * kStageB, lds + st * kStageBytes,
-                           wave, lane);
+                           wave, lane, a_pitch, a_seg);
     if constexpr (kW == 8) {
         // Two waves per SIMD: fragments single-buffered (the registers go to
         // the accumulators), the other wave's MFMAs cover the LDS reads.
@@ -560,7 +629,8 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
             barrier_lds();
             if (st >= 1 && st - 1 + kStages < nst)
                 copy_stage<kW>(Xq, N, n0, Wq, K, k0, pitch, (st - 1 + kStages) * kStageB,
-                               lds + ((st - 1) % kStages) * kStageBytes, wave, lane);
+                               lds + ((st - 1) % kStages) * kStageBytes, wave, lane, a_pitch,
+                               a_seg);
             read(st, f);
             mma(f);
         }
@@ -709,37 +779,49 @@ __global__ __launch_bounds__(256) void k_argmax_tiles(const float *__restrict__ 
 // 8192 values.
 constexpr int kQuantChunks = 32;
 
+int32_t lp_seg(int32_t D) { return (2 * D + kRowB - 1) / kRowB * kRowB; }
+
 int32_t lp_pitch(int32_t D, int32_t mode) {
+    if (mode == LBPF_F16X3) return 3 * lp_seg(D);  // weight rows [h | l | h]
     const int32_t bytes = D * (mode == LBPF_FP8_E4M3 ? 1 : 2);
     return (bytes + kRowB - 1) / kRowB * kRowB;
 }
 
+int32_t lp_pitch_features(int32_t D, int32_t mode) {
+    return mode == LBPF_F16X3 ? 2 * lp_seg(D) : lp_pitch(D, mode);  // feature rows [h | l]
+}
+
 hipError_t launch_quant_rows(const float *X, int32_t rows, int32_t D, int32_t mode, uint8_t *out,
-                             float *scales, hipStream_t s, const int32_t *n_dev) {
+                             float *scales, hipStream_t s, const int32_t *n_dev, bool weights) {
     if (rows <= 0) return hipSuccess;
-    const int32_t pitch = lp_pitch(D, mode);
-    if (D % 4 == 0 && D <= 256 * kQuantChunks && ((uintptr_t)X & 15) == 0) {
-        const dim3 grid((rows + 3) / 4);
-        if (mode == LBPF_BF16)
-            hipLaunchKernelGGL((k_quant_rows_vec<LBPF_BF16, kQuantChunks>), grid, dim3(256), 0, s,
-                               X, rows, D, pitch, out, scales, n_dev);
-        else if (mode == LBPF_FP16)
-            hipLaunchKernelGGL((k_quant_rows_vec<LBPF_FP16, kQuantChunks>), grid, dim3(256), 0, s,
-                               X, rows, D, pitch, out, scales, n_dev);
+    // Split rows: weight rows hold three segments, feature rows two.
+    const int32_t qmode = (mode == LBPF_F16X3 && weights) ? kF16X3W : mode;
+    const int32_t pitch = weights ? lp_pitch(D, mode) : lp_pitch_features(D, mode);
+    auto go = [&](auto vec_kernel, auto row_kernel) {
+        if (D % 4 == 0 && D <= 256 * kQuantChunks && ((uintptr_t)X & 15) == 0)
+            hipLaunchKernelGGL(vec_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, X, rows, D,
+                               pitch, out, scales, n_dev);
         else
-            hipLaunchKernelGGL((k_quant_rows_vec<LBPF_FP8_E4M3, kQuantChunks>), grid, dim3(256), 0,
-                               s, X, rows, D, pitch, out, scales, n_dev);
-        return hipGetLastError();
+            hipLaunchKernelGGL(row_kernel, dim3(rows), dim3(256), 0, s, X, rows, D, pitch, out,
+                               scales, n_dev);
+    };
+    switch (qmode) {
+        case LBPF_BF16:
+            go(k_quant_rows_vec<LBPF_BF16, kQuantChunks>, k_quant_rows<LBPF_BF16>);
+            break;
+        case LBPF_FP16:
+            go(k_quant_rows_vec<LBPF_FP16, kQuantChunks>, k_quant_rows<LBPF_FP16>);
+            break;
+        case LBPF_FP8_E4M3:
+            go(k_quant_rows_vec<LBPF_FP8_E4M3, kQuantChunks>, k_quant_rows<LBPF_FP8_E4M3>);
+            break;
+        case LBPF_F16X3:
+            go(k_quant_rows_vec<LBPF_F16X3, kQuantChunks>, k_quant_rows<LBPF_F16X3>);
+            break;
+        default:
+            go(k_quant_rows_vec<kF16X3W, kQuantChunks>, k_quant_rows<kF16X3W>);
+            break;
     }
-    if (mode == LBPF_BF16)
-        hipLaunchKernelGGL(k_quant_rows<LBPF_BF16>, dim3(rows), dim3(256), 0, s, X, rows, D, pitch,
-                           out, scales, n_dev);
-    else if (mode == LBPF_FP16)
-        hipLaunchKernelGGL(k_quant_rows<LBPF_FP16>, dim3(rows), dim3(256), 0, s, X, rows, D, pitch,
-                           out, scales, n_dev);
-    else
-        hipLaunchKernelGGL(k_quant_rows<LBPF_FP8_E4M3>, dim3(rows), dim3(256), 0, s, X, rows, D,
-                           pitch, out, scales, n_dev);
     return hipGetLastError();
 }
 
@@ -748,7 +830,9 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
                            float *S, int32_t *argmax, float *scratch, size_t scratch_elems,
                            hipStream_t s, const int32_t *n_dev) {
     if (N <= 0 || K <= 0) return hipSuccess;
-    const int32_t pitch = lp_pitch(D, mode);
+    const int32_t pitch = lp_pitch(D, mode);  // reduction bytes per row (weights)
+    const int32_t a_pitch = lp_pitch_features(D, mode);
+    const int32_t a_seg = mode == LBPF_F16X3 ? lp_seg(D) : 0;
     if (N >= 2 * kBigT && K >= kBigT) {
         // Large products: 256 x 256 tiles fed through the LDS ring, the
         // argmax taken in the epilogue (per tile) when its pairs fit the
@@ -759,15 +843,13 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
         float *apart = fuse ? scratch : nullptr;
         dim3 grid((uint32_t)KT * ((N + kBigT - 1) / kBigT));
         constexpr int kW = kBigWaves;
-        if (mode == LBPF_BF16)
-            hipLaunchKernelGGL((k_score_lp_big<LBPF_BF16, kW>), grid, dim3(64 * kW), 0, s, Xq, sx,
-                               N, Wq, sw, b, K, pitch, Sout, apart, n_dev);
-        else if (mode == LBPF_FP16)
-            hipLaunchKernelGGL((k_score_lp_big<LBPF_FP16, kW>), grid, dim3(64 * kW), 0, s, Xq, sx,
-                               N, Wq, sw, b, K, pitch, Sout, apart, n_dev);
-        else
-            hipLaunchKernelGGL((k_score_lp_big<LBPF_FP8_E4M3, kW>), grid, dim3(64 * kW), 0, s, Xq,
-                               sx, N, Wq, sw, b, K, pitch, Sout, apart, n_dev);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(64 * kW), 0, s, Xq, sx, N, Wq, sw, b, K, pitch,
+                               Sout, apart, n_dev, a_pitch, a_seg);
+        };
+        if (mode == LBPF_BF16) go(k_score_lp_big<LBPF_BF16, kW>);
+        else if (mode == LBPF_FP8_E4M3) go(k_score_lp_big<LBPF_FP8_E4M3, kW>);
+        else go(k_score_lp_big<LBPF_FP16, kW>);  // FP16 and split FP16
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !argmax) return e;
         if (!fuse) return launch_argmax(Sout, N, K, argmax, s, n_dev);
@@ -777,15 +859,13 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
     }
     if (!S) S = scratch;
     dim3 grid(((K + kTN - 1) / kTN) * ((N + kTM - 1) / kTM));
-    if (mode == LBPF_BF16)
-        hipLaunchKernelGGL(k_score_lp<LBPF_BF16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,
-                           pitch, S, n_dev);
-    else if (mode == LBPF_FP16)
-        hipLaunchKernelGGL(k_score_lp<LBPF_FP16>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K,
-                           pitch, S, n_dev);
-    else
-        hipLaunchKernelGGL(k_score_lp<LBPF_FP8_E4M3>, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b,
-                           K, pitch, S, n_dev);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K, pitch, S, n_dev,
+                           a_pitch, a_seg);
+    };
+    if (mode == LBPF_BF16) go(k_score_lp<LBPF_BF16>);
+    else if (mode == LBPF_FP8_E4M3) go(k_score_lp<LBPF_FP8_E4M3>);
+    else go(k_score_lp<LBPF_FP16>);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !argmax) return e;
     return launch_argmax(S, N, K, argmax, s, n_dev);

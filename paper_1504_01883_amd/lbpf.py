@@ -17,13 +17,14 @@ import torch
 _LIB_PATH = Path(__file__).resolve().parent / "liblbpf.so"
 
 LBPF_OK, LBPF_E_INVALID, LBPF_E_BUDGET, LBPF_E_HIP, LBPF_E_UNSUPPORTED = 0, -1, -2, -3, -4
-FP32, BF16, FP16, FP8_E4M3 = 0, 1, 2, 3
+FP32, BF16, FP16, FP8_E4M3, F16X3 = 0, 1, 2, 3, 4
 MAP_U59, MAP_FULL256 = 0, 1
 MOD_BOTH, MOD_GREY, MOD_DEPTH = 0, 1, 2
 MAX_SIDE = 1024
 MAX_BOXES_PER_CALL = 65536
 
-_PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
+_PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3,
+               "f16x3": F16X3}
 
 EXPORTS = [
     "lbpf_version", "lbpf_create", "lbpf_destroy", "lbpf_feature_dim", "lbpf_features",

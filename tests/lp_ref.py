@@ -75,10 +75,39 @@ def q_e4m3(x):
     return e4m3_round(y), s.astype(np.float64)
 
 
+def f16_split(x):
+    """Split FP32 rows as the library does for LBPF_F16X3: per-row
+    power-of-two scale 2^sh as for FP16, y = x 2^-sh (exact in FP32),
+    h = fp16(y), l = fp16(y - h) (the remainder is exact in FP32). Returns
+    (h, l, scale) with h and l as float64."""
+    scale = f16_row_scales(x)
+    y = (np.asarray(x, np.float64) / scale[:, None]).astype(np.float32)
+    h = y.astype(np.float16)
+    r = (y - h.astype(np.float32)).astype(np.float32)
+    l = r.astype(np.float16)
+    return h.astype(np.float64), l.astype(np.float64), scale
+
+
+def q_f16x3_features(x):
+    """Feature rows as the GEMM reads them: [h | h | l]."""
+    h, l, s = f16_split(x)
+    return np.concatenate([h, h, l], axis=1), s
+
+
+def q_f16x3_weights(w):
+    """Weight rows: [h | l | h], so the product sums hh + hl + lh."""
+    h, l, s = f16_split(w)
+    return np.concatenate([h, l, h], axis=1), s
+
+
 QUANT = {"bf16": q_bf16, "fp16": q_f16, "fp8": q_e4m3}
+QUANT_X = dict(QUANT, f16x3=q_f16x3_features)
+QUANT_W = dict(QUANT, f16x3=q_f16x3_weights)
 
 # Products each MFMA instruction sums (32x32x16 for BF16/FP16, 32x32x64 for FP8).
-K_PER_MFMA = {"bf16": 16, "fp16": 16, "fp8": 64}
+K_PER_MFMA = {"bf16": 16, "fp16": 16, "fp8": 64, "f16x3": 16}
+# Reduction length relative to D (split operands run three FP16 segments).
+D_FACTOR = {"bf16": 1, "fp16": 1, "fp8": 1, "f16x3": 3}
 
 
 def lp_tolerance(prec, D):
@@ -88,14 +117,15 @@ def lp_tolerance(prec, D):
     the k products inside one, and the epilogue's scale product, scaling and
     bias add), each contributing at most 2^-24, so n * 2^-24."""
     k = K_PER_MFMA[prec]
-    return (-(-D // k) + k + 3) * 2.0 ** -24
+    n = D * D_FACTOR[prec]
+    return (-(-n // k) + k + 3) * 2.0 ** -24
 
 
 def quantised_reference(X, W, b, prec):
     """(ref, scale): the exact FP64 scores of the quantised operands and the
     condition scale the tolerance is relative to."""
-    qx, sx = QUANT[prec](X)
-    qw, sw = QUANT[prec](W)
+    qx, sx = QUANT_X[prec](X)
+    qw, sw = QUANT_W[prec](W)
     ss = sx[:, None] * sw[None, :]
     ref = ss * (qx @ qw.T) + np.asarray(b, np.float64)[None, :]
     scale = ss * (np.abs(qx) @ np.abs(qw).T) + np.abs(np.asarray(b, np.float64))[None, :]

@@ -63,7 +63,7 @@ def lp_data(ctx, ref):
     return X, Xh, W, b, S64, A64
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8", "f16x3"])
 def test_lp_every_chunk_matches_quantised_reference(ctx, lp_data, prec):
     X, Xh, W, b, S64, A64 = lp_data
     wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda(), precision=prec)

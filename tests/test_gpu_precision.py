@@ -13,8 +13,8 @@ import pytest
 import torch
 
 from paper_1504_01883_amd import lbpf, synth
-from tests.gpu_util import require_gpu, stacked_planes
-from tests.lp_ref import QUANT, lp_tolerance
+from tests.gpu_util import require_gpu, score_tolerance, stacked_planes
+from tests.lp_ref import lp_tolerance, quantised_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,7 @@ def data(ctx):
     return hist, W, b
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8", "f16x3"])
 def test_lp_scores_match_quantised_reference(ctx, data, prec):
     hist, W, b = data
     X = hist.cpu().numpy()
@@ -45,11 +45,7 @@ def test_lp_scores_match_quantised_reference(ctx, data, prec):
     S, A = ctx.score(hist, wts)
     torch.cuda.synchronize()
     S = S.cpu().numpy().astype(np.float64)
-    qx, sx = QUANT[prec](X)
-    qw, sw = QUANT[prec](W)
-    prod = qx @ qw.T
-    ref = (sx[:, None] * sw[None, :]) * prod + b.astype(np.float64)[None, :]
-    scale = (sx[:, None] * sw[None, :]) * (np.abs(qx) @ np.abs(qw).T) + np.abs(b)[None, :]
+    ref, scale = quantised_reference(X, W, b, prec)
     err = np.abs(S - ref)
     tol = lp_tolerance(prec, ctx.dim)
     assert (err <= tol * scale + 1e-30).all(), f"max err/scale {(err / scale).max()} > {tol}"
@@ -61,7 +57,7 @@ def test_lp_report_against_fp64_oracle(ctx, ref, data):
     X = hist.cpu().numpy()
     S64, A64 = ref.score_f64(X, W, b, n_threads=8)
     lines = []
-    for prec in ("fp32", "bf16", "fp16", "fp8"):
+    for prec in ("fp32", "bf16", "fp16", "fp8", "f16x3"):
         wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda(), precision=prec)
         S, A = ctx.score(hist, wts)
         torch.cuda.synchronize()
@@ -72,7 +68,7 @@ def test_lp_report_against_fp64_oracle(ctx, ref, data):
     print("\n".join(lines))
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "f16x3"])
 def test_lp_ragged_shapes_and_argmax_only(ctx, prec):
     """N and K off the tile grid; argmax-only equals argmax of the scores."""
     rng = np.random.default_rng(5)
@@ -86,7 +82,7 @@ def test_lp_ragged_shapes_and_argmax_only(ctx, prec):
     assert S.shape == (301, 131) and torch.isfinite(S).all()
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8", "f16x3"])
 def test_lp_large_tiles_match_quantised_reference(ctx, data, prec):
     """Products with N >= 512 and K >= 256 run on the 256 x 256-tile kernel:
     N and K off its grid (1100 rows: the 300 feature rows tiled; 600
@@ -99,11 +95,31 @@ def test_lp_large_tiles_match_quantised_reference(ctx, data, prec):
     S, A = ctx.score(X, wts)
     torch.cuda.synchronize()
     S = S.cpu().numpy().astype(np.float64)
-    qx, sx = QUANT[prec](X.cpu().numpy())
-    qw, sw = QUANT[prec](W)
-    ref = (sx[:, None] * sw[None, :]) * (qx @ qw.T) + b.astype(np.float64)[None, :]
-    scale = (sx[:, None] * sw[None, :]) * (np.abs(qx) @ np.abs(qw).T) + np.abs(b)[None, :]
+    ref, scale = quantised_reference(X.cpu().numpy(), W, b, prec)
     err = np.abs(S - ref)
     tol = lp_tolerance(prec, ctx.dim)
     assert (err <= tol * scale + 1e-30).all(), f"max err/scale {(err / scale).max()} > {tol}"
     assert np.array_equal(A.cpu().numpy(), np.argmax(S.astype(np.float32), axis=1))
+
+
+@pytest.mark.parametrize("n,k", [(300, 97), (1100, 600)])
+def test_f16x3_meets_the_fp32_bar(ctx, ref, data, n, k):
+    """Split FP16 scoring against the FP64 oracle on the unquantised data: every
+    score within 1e-5 of the dot product's condition scale (the FP32 bar), and
+    the identities equal wherever the oracle's top-2 margin exceeds twice that
+    tolerance; small tiles (300 x 97) and large tiles (1100 x 600)."""
+    hist, _, _ = data
+    X = hist.repeat(4, 1)[:n].contiguous()
+    W, b = synth.synthetic_weights(k, ctx.dim, synth.W_PRECISION)
+    wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda(), precision="f16x3")
+    S, A = ctx.score(X, wts)
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    S64, A64 = ref.score_f64(Xh, W, b, n_threads=8)
+    tol = score_tolerance(Xh, W, b)
+    err = np.abs(S.cpu().numpy().astype(np.float64) - S64)
+    assert (err <= tol).all(), f"max err/tol {(err / tol).max():.3f}"
+    top2 = np.sort(S64, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 2 * tol.max(axis=1)
+    assert np.array_equal(A.cpu().numpy()[clear], A64[clear])
+    print(f"f16x3 {n}x{k}: max err / (1e-5 condition scale) {(err / tol).max():.4f}")

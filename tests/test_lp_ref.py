@@ -89,3 +89,31 @@ def test_e4m3_saturates_and_row_scales():
 @pytest.mark.parametrize("prec,D,n", [("bf16", 7552, 472 + 16 + 3), ("fp8", 7552, 118 + 64 + 3)])
 def test_lp_tolerance_counts_roundings(prec, D, n):
     assert lp_ref.lp_tolerance(prec, D) == n * 2.0 ** -24
+
+
+def test_f16_split_matches_torch_and_bounds_the_remainder():
+    """The split of LBPF_F16X3: h is torch's float16 of the row-scaled value,
+    l torch's float16 of the (exact) FP32 remainder, and h + l reproduces the
+    scaled value within 2^-22 of it plus half the smallest FP16 subnormal."""
+    rng = np.random.default_rng(23)
+    x = np.concatenate([rng.random((64, 257), dtype=np.float32) / 300.0,
+                        rng.standard_normal((64, 257)).astype(np.float32)])
+    x[3, :] = 0.0
+    x[5, 7] = 1e-30
+    h, l, scale = lp_ref.f16_split(x)
+    y = (x.astype(np.float64) / scale[:, None]).astype(np.float32)
+    th = torch.from_numpy(y).to(torch.float16)
+    assert np.array_equal(h, th.to(torch.float64).numpy())
+    rem = torch.from_numpy(y) - th.to(torch.float32)
+    assert np.array_equal(l, rem.to(torch.float16).to(torch.float64).numpy())
+    err = np.abs(y.astype(np.float64) - h - l)
+    assert (err <= 2.0 ** -22 * np.abs(y) + 2.0 ** -25).all()
+    # The three products the GEMM sums approximate the FP64 dot product of the
+    # scaled rows within 3 * 2^-22 of the condition scale (plus the floor).
+    qx, sx = lp_ref.q_f16x3_features(x[:8])
+    qw, sw = lp_ref.q_f16x3_weights(x[8:16])
+    approx = (sx[:, None] * sw[None, :]) * (qx @ qw.T)
+    exact = x[:8].astype(np.float64) @ x[8:16].astype(np.float64).T
+    cond = np.abs(x[:8].astype(np.float64)) @ np.abs(x[8:16].astype(np.float64)).T
+    floor = 257 * 2.0 ** -24 * (sx[:, None] * sw[None, :])
+    assert (np.abs(approx - exact) <= 3 * 2.0 ** -22 * cond + floor).all()
