@@ -30,6 +30,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import gc
 import sys
 import time
 
@@ -199,11 +200,23 @@ class GpuBackend:
         return (g, z)
 
     def upload(self, req: Request):
-        g, z = req.frame
-        with self.torch.cuda.stream(self.copy_stream):
-            self.grey[req.slot].copy_(g, non_blocking=True)
-            self.depth[req.slot].copy_(z, non_blocking=True)
-            self.copied[req.slot].record(self.copy_stream)
+        self.upload_many([req])
+
+    def upload_many(self, reqs: list[Request]):
+        """Copy the admitted frames to their slots on the copy stream: one
+        call for all of them, and one event that every slot of the group
+        waits on."""
+        if not reqs:
+            return
+        t = self.torch
+        dst = [self.grey[r.slot] for r in reqs] + [self.depth[r.slot] for r in reqs]
+        src = [r.frame[0] for r in reqs] + [r.frame[1] for r in reqs]
+        with t.cuda.stream(self.copy_stream):
+            t._foreach_copy_(dst, src, non_blocking=True)
+            ev = t.cuda.Event()
+            ev.record(self.copy_stream)
+        for r in reqs:
+            self.copied[r.slot] = ev
 
     def can_launch(self) -> bool:
         return bool(self.free_sets)
@@ -322,40 +335,82 @@ def poisson_arrivals(n_streams: int, fps: float, duration: float, seed: int):
     return out
 
 
-def run(backend, sched: Scheduler, arrivals, frames, warmup: float = 0.0):
+def run(backend, sched: Scheduler, arrivals, frames, warmup: float = 0.0, stats=None,
+        freeze_gc: bool = False):
     """Serve `arrivals` in real time. frames[(stream, index)] -> (frame handle,
     boxes, idents). Returns the completed requests (arrival >= warmup) and the
-    wall time of the measured window."""
+    wall time of the measured window. With a `stats` dict the loop records
+    its own cost there: iterations, the longest iteration, the share of the
+    wall time spent outside sleeps, and Python's garbage-collection pauses.
+    freeze_gc moves the objects alive at the start out of the collector's
+    reach and turns automatic collection off for the run (the loop's own
+    garbage is then freed by reference counting alone)."""
     reqs, done = [], []
+    gcs = {"n": 0, "total": 0.0, "max": 0.0, "t": 0.0}
+
+    def on_gc(phase, info):
+        if phase == "start":
+            gcs["t"] = time.perf_counter()
+        else:
+            d = time.perf_counter() - gcs["t"]
+            gcs["n"] += 1
+            gcs["total"] += d
+            gcs["max"] = max(gcs["max"], d)
+
+    if freeze_gc:
+        gc.collect()
+        gc.freeze()
+        gc.disable()
+    if stats is not None:
+        gc.callbacks.append(on_gc)
+    iters, slept, longest = 0, 0.0, 0.0
     t0 = time.perf_counter()
     ai = 0
-    while ai < len(arrivals) or not sched.idle() or backend.busy():
-        now = time.perf_counter() - t0
-        while ai < len(arrivals) and arrivals[ai][0] <= now:
-            t, s, i = arrivals[ai]
-            fr, boxes, idents = frames[(s, i)]
-            req = Request(rid=ai, stream=s, t_arrival=t0 + t, boxes=boxes, frame=fr,
-                          idents=idents)
-            reqs.append(req)
-            sched.submit(req)
-            ai += 1
-        for req in sched.admit():
-            backend.upload(req)
-        while backend.can_launch():
-            batch = sched.next_batch()
-            if not batch:
-                break
-            backend.launch(batch)
-        for batch in backend.poll():
-            sched.complete(batch)
-            done.extend(batch)
-        if ai < len(arrivals) and not backend.busy() and sched.idle():
-            nxt = arrivals[ai][0] - (time.perf_counter() - t0)
-            if nxt > 0.0005:
-                time.sleep(min(nxt, 0.002))
-        else:
-            time.sleep(0.0001)
+    try:
+        while ai < len(arrivals) or not sched.idle() or backend.busy():
+            t_it = time.perf_counter()
+            now = t_it - t0
+            while ai < len(arrivals) and arrivals[ai][0] <= now:
+                t, s, i = arrivals[ai]
+                fr, boxes, idents = frames[(s, i)]
+                req = Request(rid=ai, stream=s, t_arrival=t0 + t, boxes=boxes, frame=fr,
+                              idents=idents)
+                reqs.append(req)
+                sched.submit(req)
+                ai += 1
+            admitted = sched.admit()
+            if admitted:
+                backend.upload_many(admitted)
+            while backend.can_launch():
+                batch = sched.next_batch()
+                if not batch:
+                    break
+                backend.launch(batch)
+            for batch in backend.poll():
+                sched.complete(batch)
+                done.extend(batch)
+            t_work = time.perf_counter()
+            longest = max(longest, t_work - t_it)
+            iters += 1
+            if ai < len(arrivals) and not backend.busy() and sched.idle():
+                nxt = arrivals[ai][0] - (time.perf_counter() - t0)
+                if nxt > 0.0005:
+                    time.sleep(min(nxt, 0.002))
+            else:
+                time.sleep(0.0001)
+            slept += time.perf_counter() - t_work
+    finally:
+        if freeze_gc:
+            gc.enable()
+            gc.unfreeze()
+        if stats is not None:
+            gc.callbacks.remove(on_gc)
     end = time.perf_counter()
+    if stats is not None:
+        stats.update({"loop_iterations": iters, "longest_iteration_ms": longest * 1e3,
+                      "host_busy_fraction": 1.0 - slept / max(end - t0, 1e-9),
+                      "gc_pauses": gcs["n"], "gc_total_ms": gcs["total"] * 1e3,
+                      "gc_longest_ms": gcs["max"] * 1e3})
     measured = [r for r in done if r.t_arrival - t0 >= warmup]
     return measured, end - (t0 + warmup), reqs
 
@@ -427,7 +482,9 @@ def bench(args) -> dict:
     1-8 faces, BF16 scoring against 1024 identities; 2 s warm-up + 30 s
     measured. The same arrivals are replayed through the plain unbatched FP32
     path for comparison, and the offered rate is raised until p99 exceeds one
-    frame interval (33 ms) to find the saturation throughput."""
+    frame interval (33 ms) to find the saturation throughput. The serving loop
+    runs with Python's garbage collection frozen unless a sweep says
+    otherwise."""
     import torch
 
     from . import lbpf, synth
@@ -454,31 +511,39 @@ def bench(args) -> dict:
             handles[(s, i)] = cache[key]
         return handles
 
-    def one(rate_mult, plain=False, duration=secs, warmup=warm, track=False, graph=True):
+    def one(rate_mult, plain=False, duration=secs, warmup=warm, track=False, graph=True,
+            freeze_gc=True):
         arr = poisson_arrivals(n_streams, fps * rate_mult, warmup + duration, synth.SEED)
         be = GpuBackend(ctx, w_fp32 if plain else w_bf16, n_slots, 64, inflight=2, plain=plain,
                         track=track, graph=graph)
         frames = frames_for(be, arr)
         sch = Scheduler(n_slots, budget, max_batch_frames=64)
-        measured, wall, _ = run(be, sch, arr, frames, warmup)
+        st = {}
+        measured, wall, _ = run(be, sch, arr, frames, warmup, stats=st, freeze_gc=freeze_gc)
         out = summarize(measured, wall)
         out["deferrals"] = sch.deferrals
+        out["host_loop"] = st
         print(f"[serve] x{rate_mult:g} {'plain' if plain else ('graph' if graph else 'eager')}"
-              f"{' +track' if track else ''}: {out.get('crops_per_s', 0):.0f} crops/s, p50 "
-              f"{out.get('p50_ms', 0):.2f} ms, p99 {out.get('p99_ms', 0):.2f} ms",
-              file=sys.stderr, flush=True)
+              f"{' +track' if track else ''}{'' if freeze_gc else ' gc on'}: "
+              f"{out.get('crops_per_s', 0):.0f} crops/s, p50 {out.get('p50_ms', 0):.2f} ms, "
+              f"p99 {out.get('p99_ms', 0):.2f} ms; loop busy {st['host_busy_fraction']:.2f}, "
+              f"longest iteration {st['longest_iteration_ms']:.1f} ms, gc {st['gc_pauses']} "
+              f"pauses, longest {st['gc_longest_ms']:.1f} ms", file=sys.stderr, flush=True)
         return out
 
     fused = one(1.0)
     tracked = one(1.0, duration=min(secs, 10.0), track=True)
     plain = one(1.0, plain=True, duration=min(secs, 10.0))
     # Saturation: raise the offered rate until p99 passes one frame interval,
-    # with the captured pipeline and with eager per-batch calls.
+    # with the captured pipeline and with eager per-batch calls (garbage
+    # collection frozen in both), and with the pipeline under Python's
+    # automatic collection.
     sweeps = {}
-    for name, graph in (("graph", True), ("eager", False)):
+    for name, graph, frz in (("graph", True, True), ("eager", False, True),
+                             ("graph_gc_on", True, False)):
         sweep = []
-        for mult in (4.0, 16.0, 32.0, 64.0, 128.0):
-            r = one(mult, duration=4.0, warmup=0.5, graph=graph)
+        for mult in (4.0, 16.0, 32.0, 48.0, 64.0, 128.0):
+            r = one(mult, duration=4.0, warmup=0.5, graph=graph, freeze_gc=frz)
             r["rate_mult"] = mult
             sweep.append(r)
             if r.get("p99_ms", 1e9) > 1000.0 / fps:
@@ -501,6 +566,7 @@ def bench(args) -> dict:
                        "identities": K},
             "fused": fused, "fused_with_tracking": tracked,
             "plain_unbatched_fp32": plain, "saturation_sweep": sweep,
+            "saturation_sweep_graph_gc_on": sweeps["graph_gc_on"],
             "saturation_sweep_eager": sweeps["eager"],
             "max_crops_per_s_with_p99_under_frame_interval":
                 sat["crops_per_s"] if sat else None,

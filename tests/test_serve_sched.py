@@ -17,8 +17,8 @@ class FakeBackend:
         self.launched = []
         self.uploaded = []
 
-    def upload(self, req):
-        self.uploaded.append(req.rid)
+    def upload_many(self, reqs):
+        self.uploaded.extend(r.rid for r in reqs)
 
     def can_launch(self):
         return len(self.running) < self.inflight
