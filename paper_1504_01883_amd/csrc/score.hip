@@ -178,21 +178,6 @@ __device__ __forceinline__ void wait_vm() {
     __builtin_amdgcn_s_waitcnt((kVm & 15) | (7 << 4) | (15 << 8) | ((kVm >> 4) << 14));
 }
 
-// Wait until at most kPer * younger of this wave's copies are in flight.
-template <int kPer>
-__device__ __forceinline__ void wait_stage(int younger) {
-    switch (younger) {
-        case 0: wait_vm<0>(); break;
-        case 1: wait_vm<kPer>(); break;
-        case 2: wait_vm<2 * kPer>(); break;
-        case 3: wait_vm<3 * kPer>(); break;
-        case 4: wait_vm<4 * kPer>(); break;
-        case 5: wait_vm<5 * kPer>(); break;
-        case 6: wait_vm<6 * kPer>(); break;
-        default: wait_vm<7 * kPer>(); break;
-    }
-}
-
 // Barrier that orders LDS only: this wave's LDS reads have returned
 // (lgkmcnt 0) before it arrives. __syncthreads would also drain the copies of
 // the stages still in flight.
@@ -255,12 +240,15 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
         src[j] = (isx ? X : W) + (size_t)g * D + d0 + 4 * swz(row, pos);
         dst[j] = isx ? (wave * 32 + j * 8) * kSlice : kTM * kSlice + (wave * kWRows + (j - 4) * 8) * kSlice;
     }
-    auto copy = [&](int st) {
+    // Copy j of stage st into ring slot st % kRingN. Stages past the last one
+    // re-read the last stage's slice into a slot nobody reads again, so every
+    // step issues the same copies: the loop body has no branch and the copies
+    // can be spread between its matrix instructions.
+    auto copy1 = [&](int st, int j) {
         uint8_t *stage = lds + (st % kRingN) * kStage;
-#pragma unroll
-        for (int j = 0; j < kCopies; ++j)
-            __builtin_amdgcn_global_load_lds((glb_void_t *)(src[j] + st * (kSlice / 4)),
-                                             (lds_void_t *)(stage + dst[j]), 16, 0, 0);
+        const int sg = min(st, nst - 1);
+        __builtin_amdgcn_global_load_lds((glb_void_t *)(src[j] + sg * (kSlice / 4)),
+                                         (lds_void_t *)(stage + dst[j]), 16, 0, 0);
     };
 
     const int fr = lane & 31, fq = lane >> 5;
@@ -281,52 +269,65 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
     struct Frag {
         floatx4 a[2][4], b[kJB][4];
     };
-    auto read = [&](int st, Frag &f) {
+    // Fragments of feature chunk p (4 floats of each lane's row) of stage st.
+    auto read_p = [&](int st, Frag &f, int p) {
         const uint8_t *stage = lds + (st % kRingN) * kStage;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int i = 0; i < 2; ++i)
+            f.a[i][p] = *reinterpret_cast<const floatx4 *>(stage + oa[i][p]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                f.a[i][p] = *reinterpret_cast<const floatx4 *>(stage + oa[i][p]);
-#pragma unroll
-            for (int j = 0; j < kJB; ++j)
-                f.b[j][p] = *reinterpret_cast<const floatx4 *>(stage + ob[j][p]);
-        }
+        for (int j = 0; j < kJB; ++j)
+            f.b[j][p] = *reinterpret_cast<const floatx4 *>(stage + ob[j][p]);
     };
     floatx16 acc[2][kJB];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < kJB; ++j) acc[i][j] = floatx16{};
+    auto mma_p = [&](const Frag &f, int p) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < kJB; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[i][p][c], f.b[j][p][c],
+                                                                      acc[i][j], 0, 0, 0);
+    };
     auto mma = [&](const Frag &f) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < kJB; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[i][p][c], f.b[j][p][c],
-                                                                          acc[i][j], 0, 0, 0);
+        for (int p = 0; p < 4; ++p) mma_p(f, p);
     };
     // Stage st's buffer is free once its fragments are in registers (read
     // during the previous step, before this step's barrier), so the copy of
-    // stage st + kRingN goes there: kRingN - 1 stages stay in flight.
+    // stage st + kRingN goes there: kRingN - 1 stages stay in flight. With a
+    // single wave per SIMD the matrix core idles whenever this wave stalls on
+    // issuing memory instructions, so each step runs as four groups, one per
+    // feature chunk p: a share of the copies, the next stage's chunk-p
+    // fragments, and the current stage's chunk-p MFMAs. The scheduling
+    // barriers keep the groups apart.
     auto step = [&](int st, const Frag &cur, Frag &nxt) {
-        wait_stage<kCopies>(min(nst - 2 - st, kRingN - 2));
+        wait_vm<(kRingN - 2) * kCopies>();
         barrier_lds();
-        if (st + kRingN < nst) copy(st + kRingN);
-        read(st + 1, nxt);
-        mma(cur);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+#pragma unroll
+            for (int j = 0; j < kCopies; ++j)
+                if (j % 4 == p) copy1(st + kRingN, j);
+            read_p(st + 1, nxt, p);
+            mma_p(cur, p);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     };
 #pragma unroll
     for (int st = 0; st < kRingN; ++st)
-        if (st < nst) copy(st);
+#pragma unroll
+        for (int j = 0; j < kCopies; ++j) copy1(st, j);
     Frag f0, f1;
-    wait_stage<kCopies>(min(nst - 1, kRingN - 1));
+    wait_vm<(kRingN - 1) * kCopies>();
     barrier_lds();
-    read(0, f0);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) read_p(0, f0, p);
     int st = 0;
     for (; st + 2 < nst; st += 2) {
         step(st, f0, f1);
@@ -338,6 +339,9 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
     } else {
         mma(f0);
     }
+    // The copies past the last stage must land before the workgroup's LDS
+    // is released.
+    wait_vm<0>();
 
     // 32 x 32 block layout: register r of lane l is row 8 (r / 4) + 4 (l / 32)
     // + r % 4, column l % 32.
