@@ -26,12 +26,13 @@
 //                            channel, mask off, wide windows).
 //
 // Default configuration, per crop:
-//   * Median: wave 0 estimates it from 64 pixels on an 8 x 8 grid; one pass
-//     over the crop then histograms the 256 mm window around the estimate
-//     (1 mm bins, LDS atomics on well-spread addresses) and counts non-zero
-//     pixels and pixels above the window's start in packed 16-bit registers;
-//     when the median falls in the window the histogram gives it, otherwise
-//     an exact two-level radix select (high byte, then low byte) runs.
+//   * Median: the four waves each estimate it from 64 pixels of a 16 x 16
+//     sampling grid; one pass over the crop then histograms the 64 mm window
+//     centred on the combined estimate (1 mm bins, LDS atomics) and counts
+//     non-zero pixels and pixels above the window's start in packed 16-bit
+//     registers; when the median falls in the window the histogram gives
+//     it, otherwise an exact two-level radix select (high byte, then low
+//     byte) runs.
 //   * Codes: lanes own 4 adjacent columns and walk down a band of rows with a
 //     3-row register window. Each pixel is packed as (grey | d' << 16) with
 //     d' = clamp(d - (m - window), 0, 2 window) (0 for d = 0): clamping keeps
@@ -367,7 +368,7 @@ __device__ __forceinline__ void median_count(uint32_t q, uint32_t lolo, uint32_t
 // End of the median pass for a block of kNW waves: totals over the block,
 // then the lower median's rank looked up in the window histogram. Returns
 // the median, -1 when the crop has no depth, -2 when the median lies outside
-// [lo, lo + 256) (the caller then runs the exact radix select). All threads
+// [lo, lo + kMedWin) (the caller then runs the exact radix select). All threads
 // call it; it ends with a barrier.
 template <int kNW>
 __device__ __forceinline__ int32_t median_finish(MedianScratch &ms, uint32_t *sh_red,
@@ -402,7 +403,7 @@ __device__ __forceinline__ int32_t median_finish(MedianScratch &ms, uint32_t *sh
     return bin >= 0 ? lo + bin : -2;
 }
 
-// The 64-sample estimate of the median (wave 0 only): the lower median of the
+// One wave's 64-sample estimate of the median: the lower median of the
 // non-zero values among `v` (one per lane), or 1000 when all are zero. A binary
 // search over the value range finds the smallest t with more than `rank`
 // non-zero samples <= t, each count a ballot (16 steps of one compare).
@@ -423,12 +424,13 @@ __device__ __forceinline__ uint32_t median_estimate(uint32_t v) {
 }
 
 // Exact lower median of the crop's non-zero depth, -1 if none.
-//  1. Wave 0 estimates it: the lower median of the non-zero values among 64
-//     pixels on an 8 x 8 grid.
-//  2. One pass over the crop: a 1 mm histogram of the 256 values
-//     [lo, lo + 256) around the estimate (LDS atomics on well-spread
-//     addresses), and per-thread counts of the non-zero pixels and of those
-//     below the window (packed 16-bit arithmetic, no atomics).
+//  1. Each wave estimates it as the lower median of the non-zero values
+//     among 64 pixels of a 16 x 16 sampling grid (wave w takes the grid rows
+//     w, w + 4, ...); the estimate is the mean of the middle two of the four.
+//  2. One pass over the crop: a 1 mm histogram of the kMedWin values
+//     [lo, lo + kMedWin) centred on the estimate (LDS atomics), and
+//     per-thread counts of the non-zero pixels and of those below the window
+//     (packed 16-bit arithmetic, no atomics).
 //  3. When the median's rank falls inside the window, the window histogram
 //     gives it exactly; otherwise the two-level radix select runs.
 // All threads of the block call it.
