@@ -209,7 +209,7 @@ def run_ragged(args, ctx, host):
         batch.set_launch(persistent=p, wg_per_cu=m, row_prefetch=pf, sorted=so)
         tuned = {"cfg": batch.get_launch(), "us": None, "cached": False, "fixed": True}
     else:
-        tuned = tune.tuned(ctx, batch, hist, n, area, reps=3, retune=True)
+        tuned = tune.tuned(ctx, batch, hist, n, area, reps=10, retune=True)
     graph = ctx.graph(batch, hist)  # the feature launch, captured once
 
     def step(i, ev):

@@ -273,8 +273,9 @@ typedef struct lbpf_launch_cfg {
 lbpf_status lbpf_batch_set_launch(lbpf_batch *batch, const lbpf_launch_cfg *cfg);
 lbpf_status lbpf_batch_get_launch(const lbpf_batch *batch, lbpf_launch_cfg *cfg);
 
-/* Autotuner: time every candidate launch shape on this batch (reps timed
- * launches each, HIP events on `stream`, synchronous), keep the fastest in
+/* Autotuner: time every candidate launch shape on this batch (two rounds
+ * over the candidates, each timing one warm-up launch then reps launches
+ * with HIP events on `stream`; synchronous), keep the fastest average in
  * the batch and report it (best_out, best_us_out may be NULL). hist is a
  * DEVICE [n][D] FP32 scratch the runs write into. */
 lbpf_status lbpf_tune_batch(lbpf_ctx *ctx, lbpf_batch *batch, float *hist, int32_t reps,

@@ -433,7 +433,12 @@ lbpf_status lbpf_tune_batch(lbpf_ctx *ctx, lbpf_batch *batch, float *hist, int32
     float best = 0.f;
     lbpf_launch_cfg best_cfg = cands[0];
     lbpf_status st = LBPF_OK;
-    for (const auto &cand : cands) {
+    // Two rounds over the candidates, so a shape timed while the device was
+    // still warming up (clocks, caches) gets a second chance; the fastest
+    // average of a round wins.
+    std::vector<lbpf_launch_cfg> rounds(cands);
+    rounds.insert(rounds.end(), cands.begin(), cands.end());
+    for (const auto &cand : rounds) {
         lbpf_batch_set_launch(batch, &cand);
         er = launch_features(batch->d_crops, batch->n, ctx->fp, ctx->d_bins, hist, nullptr, s,
                              batch->lc, batch->d_order, batch->d_queue, ctx->num_cus);
