@@ -332,6 +332,106 @@ lbpf_status lbpf_pipeline_launch(lbpf_pipeline *pipeline, const lbpf_image *imag
 int32_t lbpf_pipeline_max_boxes(const lbpf_pipeline *pipeline);
 void lbpf_pipeline_destroy(lbpf_pipeline *pipeline);
 
+/* Native serving loop (Sec. 3's per-frame loop of detection, mapping,
+ * features and classification, here for frames from many cameras at once):
+ * a library thread admits frames, uploads them and runs batches, so that no
+ * per-frame step needs the caller's thread.
+ *
+ * Every frame is frame_w x frame_h, a grey u8 plane and a depth u16 plane
+ * with packed rows. The server owns n_slots device frame slots. Submitted
+ * requests are released at their arrival time on the server clock, then
+ * admitted first come, first served into a free slot while the bytes of all
+ * admitted frames (3 frame_w frame_h each) stay within budget_bytes; a
+ * request that does not fit waits, and nothing behind it overtakes it.
+ * Admitted frames are copied host -> device on the server's copy stream.
+ * Whenever one of the `inflight` batch sets is free, up to max_batch_frames
+ * admitted frames form a batch: one captured-pipeline replay
+ * (lbpf_pipeline_*: box table, features, scores of the weights' precision,
+ * argmax, identities copied to pinned host memory) on the set's own stream,
+ * after the copies of its frames. Frames arriving while batches run join the
+ * next batch (continuous batching). When the server thread sees a batch's
+ * completion it frees the slots and records each request's result and
+ * completion time. Requirements as for lbpf_pipeline_create. */
+typedef struct lbpf_server lbpf_server;
+
+typedef struct lbpf_server_cfg {
+    int32_t frame_w, frame_h;     /* 3 .. 4096 each */
+    int32_t n_slots;              /* device frame slots, 1 .. 4096 */
+    int64_t budget_bytes;         /* >= one frame's 3 frame_w frame_h bytes */
+    int32_t max_batch_frames;     /* 1 .. n_slots */
+    int32_t max_boxes_per_frame;  /* 1 .. 64 */
+    int32_t inflight;             /* batch sets (streams, pipelines), 1 .. 8 */
+} lbpf_server_cfg;
+
+/* One frame to serve. t_arrival: seconds on the server clock
+ * (lbpf_server_clock); arrivals must not decrease across submissions.
+ * grey, depth: HOST [frame_h][frame_w] planes, read by asynchronous copies,
+ * so they should be pinned (hipHostMalloc, or pinned torch tensors); they
+ * must stay valid and unchanged until the request's result has been polled.
+ * boxes: HOST [n_boxes][4] int32 (x, y, w, h), each 3 <= w, h and inside the
+ * frame; copied at submission. */
+typedef struct lbpf_request {
+    int64_t id;
+    double t_arrival;
+    const uint8_t *grey;
+    const uint16_t *depth;
+    const int32_t *boxes;
+    int32_t n_boxes;
+} lbpf_request;
+
+/* A served frame: its identities (argmax over the enrolled identities, one
+ * per box in submission order) are argmax[argmax_offset .. + n_boxes) of
+ * the lbpf_server_poll call that returned it. t_done: server-clock time at
+ * which the server thread saw the batch's completion. */
+typedef struct lbpf_result {
+    int64_t id;
+    double t_arrival, t_done;
+    int32_t n_boxes;
+    int32_t argmax_offset;
+} lbpf_result;
+
+typedef struct lbpf_server_stats {
+    int64_t batches, frames, boxes;
+    int64_t deferrals;         /* loop iterations in which the budget or slots held a request back */
+    int64_t loop_iterations;
+    double busy_seconds;       /* server thread time outside idle waits */
+    double seconds;            /* server clock now */
+} lbpf_server_stats;
+
+/* Allocates the frame slots, per batch set a stream, a pipeline and its
+ * hist / argmax buffers (charged to the context's budget), and starts the
+ * server thread. ctx and weights must outlive the server; while it runs,
+ * other threads may use the context for calls that neither create nor
+ * destroy objects. Errors: LBPF_E_INVALID (configuration out of range),
+ * LBPF_E_BUDGET, LBPF_E_UNSUPPORTED (as lbpf_pipeline_create), LBPF_E_HIP. */
+lbpf_status lbpf_server_create(lbpf_ctx *ctx, const lbpf_weights *weights,
+                               const lbpf_server_cfg *cfg, lbpf_server **out);
+
+/* Seconds since the server was created (steady clock). */
+double lbpf_server_clock(const lbpf_server *server);
+
+/* Queue n requests (HOST array). Validates all of them first: on
+ * LBPF_E_INVALID (NULL plane, box count or box out of range, an arrival
+ * earlier than one already submitted) none is queued. Thread-safe against
+ * lbpf_server_poll. Also returns the server thread's error (LBPF_E_HIP) once
+ * it has stopped on one. */
+lbpf_status lbpf_server_submit(lbpf_server *server, const lbpf_request *requests, int32_t n);
+
+/* Move up to max_results finished requests (oldest first) into results
+ * (HOST) and their identities into argmax (HOST, max_argmax entries); stops
+ * early when the next request's boxes would not fit. *n_out: results
+ * written. Never blocks on the GPU. Errors: LBPF_E_INVALID (NULL, negative
+ * sizes), LBPF_E_HIP (the server thread stopped on a HIP error; results
+ * finished before it are still returned). */
+lbpf_status lbpf_server_poll(lbpf_server *server, lbpf_result *results, int32_t max_results,
+                             int32_t *argmax, int32_t max_argmax, int32_t *n_out);
+
+lbpf_status lbpf_server_get_stats(const lbpf_server *server, lbpf_server_stats *out);
+
+/* Stops the server: requests not yet in a batch are dropped, batches on the
+ * device are waited for; then frees everything the server allocated. */
+void lbpf_server_destroy(lbpf_server *server);
+
 /* Enrol K identities: W DEVICE [K][D] FP32 row-major, b DEVICE [K] FP32.
  * The library copies them (and, for BF16/FP16/FP8, quantises them) into a
  * weights object it owns; the caller's buffers may be freed once `stream`

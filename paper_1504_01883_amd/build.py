@@ -16,7 +16,7 @@ OBJ = PKG / "_build"
 LIB = PKG / "liblbpf.so"
 
 SOURCES = ["features.hip", "score.hip", "score_lp.hip", "plain.hip", "warp.hip", "train.hip",
-           "track.hip", "noalloc.hip", "runtime.cpp", "tables.cpp"]
+           "track.hip", "noalloc.hip", "runtime.cpp", "server.cpp", "tables.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "ctx_internal.h"
 #include "lbpf_internal.h"
 
 using namespace lbpf;
@@ -179,6 +180,10 @@ lbpf_status resolve(const lbpf_ctx *ctx, const lbpf_image *images, int32_t n_ima
 }
 
 }  // namespace
+
+bool lbpf::ctx_charge(lbpf_ctx *ctx, size_t bytes) { return charge(ctx, bytes); }
+void lbpf::ctx_refund(lbpf_ctx *ctx, size_t bytes) { ctx->used -= bytes; }
+int lbpf::ctx_device(const lbpf_ctx *ctx) { return ctx->device; }
 
 extern "C" {
 

@@ -35,7 +35,9 @@ EXPORTS = [
     "lbpf_graph_create", "lbpf_graph_launch", "lbpf_graph_destroy", "lbpf_warp_crop_bytes",
     "lbpf_features_warped", "lbpf_train_workspace_bytes", "lbpf_train_ovr", "lbpf_track",
     "lbpf_score_noalloc", "lbpf_pipeline_create", "lbpf_pipeline_launch",
-    "lbpf_pipeline_max_boxes", "lbpf_pipeline_destroy",
+    "lbpf_pipeline_max_boxes", "lbpf_pipeline_destroy", "lbpf_server_create",
+    "lbpf_server_clock", "lbpf_server_submit", "lbpf_server_poll", "lbpf_server_get_stats",
+    "lbpf_server_destroy",
 ]
 
 
@@ -88,6 +90,32 @@ class LaunchCfg(ctypes.Structure):
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("frame_w", ctypes.c_int32), ("frame_h", ctypes.c_int32),
+                ("n_slots", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
+                ("max_batch_frames", ctypes.c_int32), ("max_boxes_per_frame", ctypes.c_int32),
+                ("inflight", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_int64), ("frames", ctypes.c_int64),
+                ("boxes", ctypes.c_int64), ("deferrals", ctypes.c_int64),
+                ("loop_iterations", ctypes.c_int64), ("busy_seconds", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# lbpf_request and lbpf_result as numpy record types (C layout, natural
+# alignment), so that thousands of requests are marshalled as one array.
+REQUEST_DTYPE = np.dtype([("id", np.int64), ("t_arrival", np.float64), ("grey", np.uint64),
+                          ("depth", np.uint64), ("boxes", np.uint64), ("n_boxes", np.int32),
+                          ("pad", np.int32)])
+RESULT_DTYPE = np.dtype([("id", np.int64), ("t_arrival", np.float64), ("t_done", np.float64),
+                         ("n_boxes", np.int32), ("argmax_offset", np.int32)])
 
 
 class FeatureCfg(ctypes.Structure):
@@ -144,6 +172,12 @@ def load():
         "lbpf_pipeline_launch": (st, [vp, vp, i32, vp, i32, vp]),
         "lbpf_pipeline_max_boxes": (i32, [vp]),
         "lbpf_pipeline_destroy": (None, [vp]),
+        "lbpf_server_create": (st, [vp, vp, vp, vp]),
+        "lbpf_server_clock": (ctypes.c_double, [vp]),
+        "lbpf_server_submit": (st, [vp, vp, i32]),
+        "lbpf_server_poll": (st, [vp, vp, i32, vp, i32, vp]),
+        "lbpf_server_get_stats": (st, [vp, vp]),
+        "lbpf_server_destroy": (None, [vp]),
         "lbpf_status_string": (ctypes.c_char_p, [st]),
         "lbpf_last_error": (ctypes.c_char_p, []),
     }
@@ -322,6 +356,95 @@ class Pipeline:
         if self._h:
             load().lbpf_pipeline_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The native serving loop (lbpf_server_*): a library thread admits,
+    uploads and batches frames; submit() queues requests, poll() collects
+    the finished ones. Host frame planes must be pinned CPU tensors and stay
+    alive until their results have been polled (the server keeps references
+    to the tensors of submitted requests until then)."""
+
+    def __init__(self, ctx: "Context", weights: "Weights", frame_w: int, frame_h: int,
+                 n_slots: int, budget_bytes: int, max_batch_frames: int,
+                 max_boxes_per_frame: int = 8, inflight: int = 2):
+        self._ctx, self._weights = ctx, weights  # must outlive the server
+        cfg = ServerCfg(frame_w, frame_h, n_slots, budget_bytes, max_batch_frames,
+                        max_boxes_per_frame, inflight)
+        h = ctypes.c_void_p()
+        _check(load().lbpf_server_create(ctx._h, weights._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.frame_w, self.frame_h = frame_w, frame_h
+        self.max_boxes_per_frame = max_boxes_per_frame
+        self._keep: dict[int, tuple] = {}  # id -> (grey, depth) of requests in flight
+
+    def clock(self) -> float:
+        return float(load().lbpf_server_clock(self._h))
+
+    def submit(self, ids, t_arrival, frames, boxes):
+        """Queue requests: ids [n] int64, t_arrival [n] seconds on the server
+        clock (non-decreasing), frames: n (grey u8 [H, W], depth int16/u16
+        [H, W]) pinned CPU tensors, boxes: n arrays [k, 4] (x, y, w, h)."""
+        n = len(ids)
+        req = np.zeros(n, REQUEST_DTYPE)
+        counts = np.array([len(b) for b in boxes], np.int64)
+        flat = (np.ascontiguousarray(np.concatenate([np.asarray(b, np.int32).reshape(-1, 4)
+                                                     for b in boxes]))
+                if n else np.zeros((0, 4), np.int32))
+        offs = np.concatenate([[0], np.cumsum(counts)[:-1]]) if n else counts
+        gp, zp = req["grey"], req["depth"]
+        seen: dict[int, tuple] = {}  # frames repeat: check each tensor pair once
+        for i, f in enumerate(frames):
+            ptrs = seen.get(id(f))
+            if ptrs is None:
+                g, z = f
+                if g.is_cuda or z.is_cuda or not (g.is_pinned() and z.is_pinned()):
+                    raise ValueError("server frames must be pinned CPU tensors")
+                if (tuple(g.shape) != (self.frame_h, self.frame_w) or g.shape != z.shape or
+                        g.element_size() != 1 or z.element_size() != 2 or
+                        not (g.is_contiguous() and z.is_contiguous())):
+                    raise ValueError("frame planes must be contiguous u8 / 16-bit "
+                                     "[frame_h, frame_w]")
+                ptrs = seen[id(f)] = (g.data_ptr(), z.data_ptr())
+            gp[i], zp[i] = ptrs
+        req["id"] = np.asarray(ids, np.int64)
+        req["t_arrival"] = np.asarray(t_arrival, np.float64)
+        req["n_boxes"] = counts
+        req["boxes"] = flat.ctypes.data + 16 * offs
+        _check(load().lbpf_server_submit(self._h, req.ctypes.data, n))
+        for i, f in zip(req["id"].tolist(), frames):
+            self._keep[i] = f
+
+    def poll(self, max_results: int = 4096):
+        """Finished requests (oldest first) as a RESULT_DTYPE array and the
+        identities: result i's boxes are argmax[argmax_offset : + n_boxes]."""
+        res = np.zeros(max_results, RESULT_DTYPE)
+        amax = np.zeros(max_results * self.max_boxes_per_frame, np.int32)
+        n = ctypes.c_int32()
+        st = load().lbpf_server_poll(self._h, res.ctypes.data, max_results, amax.ctypes.data,
+                                     len(amax), ctypes.byref(n))
+        res = res[:n.value]
+        for i in res["id"].tolist():
+            self._keep.pop(i, None)
+        _check(st)
+        return res, amax
+
+    def stats(self) -> dict:
+        out = ServerStats()
+        _check(load().lbpf_server_get_stats(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def close(self):
+        if self._h:
+            load().lbpf_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:
@@ -510,6 +633,12 @@ class Context:
 
     def pipeline(self, weights: Weights, max_boxes: int) -> Pipeline:
         return Pipeline(self, weights, max_boxes)
+
+    def server(self, weights: Weights, frame_w: int, frame_h: int, n_slots: int,
+               budget_bytes: int, max_batch_frames: int, max_boxes_per_frame: int = 8,
+               inflight: int = 2) -> Server:
+        return Server(self, weights, frame_w, frame_h, n_slots, budget_bytes, max_batch_frames,
+                      max_boxes_per_frame, inflight)
 
     def weights(self, W: torch.Tensor, b: torch.Tensor, precision="fp32") -> Weights:
         return Weights(self, W, b, precision)
