@@ -73,7 +73,8 @@ typedef enum lbpf_precision {
     LBPF_FP32 = 0,       /* FP32 operands, FP32 MFMA accumulation */
     LBPF_BF16 = 1,       /* BF16 operands (round to nearest even), FP32 accumulation */
     LBPF_FP16 = 2,       /* FP16 operands with per-row power-of-two scales */
-    LBPF_FP8_E4M3 = 3,   /* OCP FP8 e4m3 operands with per-row amax/448 scales */
+    LBPF_FP8_E4M3 = 3,   /* OCP FP8 e4m3 operands with per-row amax/448 scales
+                            (encoded as x * (448/amax) in FP32, RNE, saturating) */
     LBPF_F16X3 = 4       /* FP32 operands split into FP16 high and low parts (per-row
                             power-of-two scales); scores = hi hi + hi lo + lo hi on FP16
                             matrix cores with FP32 accumulation: FP32-level accuracy */

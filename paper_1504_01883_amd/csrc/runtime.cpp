@@ -635,9 +635,17 @@ lbpf_status lbpf_score(lbpf_ctx *ctx, const float *hist, int32_t N, const lbpf_w
     hipStream_t s = (hipStream_t)stream;
     const size_t K = (size_t)w->K, D = (size_t)w->D;
     // Rows per pass: all of them when scores go to the caller's buffer,
-    // otherwise as many as the context's score scratch holds.
+    // otherwise as many as the context's score scratch holds. Reduced
+    // precision passes are chunks of quantised rows; an argmax-only chunk
+    // keeps only per-tile (score, identity) pairs in the scratch (the
+    // small-product kernel blocks its rows to fit), so whole chunks run.
     int32_t rows = scores_opt ? N : (int32_t)std::max<size_t>(1, ctx->scores_elems / K);
-    if (w->prec != LBPF_FP32) rows = std::min(rows, kLpChunkRows);
+    if (w->prec != LBPF_FP32) {
+        const size_t tiles = (K + 255) / 256;
+        if (!scores_opt && 2 * (size_t)kLpChunkRows * tiles <= ctx->scores_elems)
+            rows = kLpChunkRows;
+        rows = std::min(rows, kLpChunkRows);
+    }
     // FP32 products too small to fill the GPU with 128 x 128 tiles split D
     // (partials in the context's scratch).
     const int32_t splits =

@@ -7,7 +7,11 @@
 //         largest magnitude, so the row's largest value lands in [2^14, 2^15)
 //         and the scaling itself is exact;
 //   FP8 : OCP e4m3 (bias 7, max 448, no infinities), per-row scale
-//         s = amax / 448, x / s rounded to nearest even and saturated.
+//         s = amax / 448 and encoding factor r = 448 / amax (each one FP32
+//         division per row); x r (FP32 product) rounded to nearest even on
+//         the e4m3 grid and saturated. One multiply per element instead of a
+//         division; s r differs from 1 by at most 2^-23, far below e4m3's
+//         2^-4 step.
 // Quantised rows are stored with a row pitch rounded up to 128 bytes, zero
 // padded, so every k-stage of the GEMM is a whole 128-byte chunk. Rows of up
 // to 8192 values are quantised by k_quant_rows_vec in one read (the row held
@@ -27,6 +31,8 @@
 // all 32 banks), and the next stage's tiles are loaded into registers while
 // the current one is multiplied.
 #include "lbpf_internal.h"
+
+#include <algorithm>
 
 namespace lbpf {
 
@@ -163,8 +169,9 @@ __global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ X,
         }
     } else {
         const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
+        const float f = amax > 0.0f ? 448.0f / amax : 1.0f;
         if (threadIdx.x == 0) scales[r] = s;
-        for (int i = threadIdx.x; i < pitch; i += 256) o[i] = i < D ? to_e4m3_rne_sat(x[i] / s) : 0;
+        for (int i = threadIdx.x; i < pitch; i += 256) o[i] = i < D ? to_e4m3_rne_sat(x[i] * f) : 0;
     }
 }
 
@@ -236,13 +243,14 @@ __global__ __launch_bounds__(256) void k_quant_rows_vec(const float *__restrict_
     }
     if constexpr (kMode == LBPF_FP8_E4M3) {
         const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
+        const float f = amax > 0.0f ? 448.0f / amax : 1.0f;
         if (lane == 0) scales[r] = s;
 #pragma unroll
         for (int c = 0; c < kC; ++c) {
             const int q = c * 64 + lane;
             if (q < nq) {
-                const uint32_t w = e4m3_bits(v[c].x / s) | (e4m3_bits(v[c].y / s) << 8) |
-                                   (e4m3_bits(v[c].z / s) << 16) | (e4m3_bits(v[c].w / s) << 24);
+                const uint32_t w = e4m3_bits(v[c].x * f) | (e4m3_bits(v[c].y * f) << 8) |
+                                   (e4m3_bits(v[c].z * f) << 16) | (e4m3_bits(v[c].w * f) << 24);
                 *reinterpret_cast<uint32_t *>(o + 4 * q) = w;
             }
         }
@@ -857,18 +865,29 @@ hipError_t launch_score_lp(const uint8_t *Xq, const float *sx, int32_t N, const 
                            argmax, n_dev);
         return hipGetLastError();
     }
-    if (!S) S = scratch;
-    dim3 grid(((K + kTN - 1) / kTN) * ((N + kTM - 1) / kTM));
-    auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, Xq, sx, N, Wq, sw, b, K, pitch, S, n_dev,
-                           a_pitch, a_seg);
-    };
-    if (mode == LBPF_BF16) go(k_score_lp<LBPF_BF16>);
-    else if (mode == LBPF_FP8_E4M3) go(k_score_lp<LBPF_FP8_E4M3>);
-    else go(k_score_lp<LBPF_FP16>);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !argmax) return e;
-    return launch_argmax(S, N, K, argmax, s, n_dev);
+    // Small products. Without S the scores go through the scratch, in row
+    // blocks that fit it (one block when the row count is on the device).
+    int32_t blk = N;
+    if (!S) {
+        if (!n_dev) blk = (int32_t)std::min<size_t>((size_t)N, scratch_elems / (size_t)K);
+        if (blk < 1 || (size_t)blk * K > scratch_elems) return hipErrorInvalidValue;
+    }
+    for (int32_t r0 = 0; r0 < N; r0 += blk) {
+        const int32_t n = std::min(blk, N - r0);
+        float *Sb = S ? S + (size_t)r0 * K : scratch;
+        dim3 grid(((K + kTN - 1) / kTN) * ((n + kTM - 1) / kTM));
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, Xq + (size_t)r0 * a_pitch, sx + r0, n,
+                               Wq, sw, b, K, pitch, Sb, n_dev, a_pitch, a_seg);
+        };
+        if (mode == LBPF_BF16) go(k_score_lp<LBPF_BF16>);
+        else if (mode == LBPF_FP8_E4M3) go(k_score_lp<LBPF_FP8_E4M3>);
+        else go(k_score_lp<LBPF_FP16>);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && argmax) e = launch_argmax(Sb, n, K, argmax + r0, s, n_dev);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lbpf

@@ -11,8 +11,8 @@ documented operand rules:
   in [2^14, 2^15); the scaling is exact and the conversion rounds to nearest
   even;
 * FP8 e4m3 (OCP: bias 7, largest finite 448, no infinities): per-row scale
-  s = amax / 448 (FP32), x / s in FP32, rounded to nearest even on the e4m3
-  grid and saturated at 448.
+  s = amax / 448 and factor r = 448 / amax (each an FP32 division), x r in
+  FP32, rounded to nearest even on the e4m3 grid and saturated at 448.
 
 The FP8 rounding is written as a search over the 127 non-negative e4m3 values
 (decoded from the format's definition), not as bit arithmetic, and all three
@@ -69,9 +69,16 @@ def e4m3_row_scales(x):
     return np.where(amax > 0, amax / np.float32(448.0), np.float32(1.0)).astype(np.float32)
 
 
+def e4m3_row_factors(x):
+    amax = np.abs(x).max(axis=1).astype(np.float32)
+    safe = np.where(amax > 0, amax, np.float32(1.0)).astype(np.float32)
+    return np.where(amax > 0, np.float32(448.0) / safe, np.float32(1.0)).astype(np.float32)
+
+
 def q_e4m3(x):
     s = e4m3_row_scales(x)
-    y = (x.astype(np.float32) / s[:, None]).astype(np.float32)
+    r = e4m3_row_factors(x)
+    y = (x.astype(np.float32) * r[:, None]).astype(np.float32)
     return e4m3_round(y), s.astype(np.float64)
 
 

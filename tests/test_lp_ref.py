@@ -84,6 +84,13 @@ def test_e4m3_saturates_and_row_scales():
     # the row maximum maps onto (or within rounding of) 448
     assert (np.abs(q).max(axis=1) >= 416.0).all()
     assert np.allclose(s, np.abs(x).max(axis=1) / 448.0, rtol=2 ** -23)
+    # encoding: x times the row factor 448 / amax (both FP32), then torch's
+    # saturating float8_e4m3fn rounding
+    r = lp_ref.e4m3_row_factors(x)
+    assert np.array_equal(r, np.float32(448.0) / np.abs(x).max(axis=1).astype(np.float32))
+    y = np.clip(x * r[:, None], -448.0, 448.0).astype(np.float32)
+    want = torch.from_numpy(y).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(q, want)
 
 
 @pytest.mark.parametrize("prec,D,n", [("bf16", 7552, 472 + 16 + 3), ("fp8", 7552, 118 + 64 + 3)])
