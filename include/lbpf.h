@@ -344,7 +344,8 @@ void lbpf_pipeline_destroy(lbpf_pipeline *pipeline);
  * admitted first come, first served into a free slot while the bytes of all
  * admitted frames (3 frame_w frame_h each) stay within budget_bytes; a
  * request that does not fit waits, and nothing behind it overtakes it.
- * Admitted frames are copied host -> device on the server's copy stream.
+ * Admitted frames are copied host -> device on the server's copy streams
+ * (only the rows their boxes span).
  * Whenever one of the `inflight` batch sets is free, up to max_batch_frames
  * admitted frames form a batch: one captured-pipeline replay
  * (lbpf_pipeline_*: box table, features, scores of the weights' precision,
@@ -362,6 +363,8 @@ typedef struct lbpf_server_cfg {
     int32_t max_batch_frames;     /* 1 .. n_slots */
     int32_t max_boxes_per_frame;  /* 1 .. 64 */
     int32_t inflight;             /* batch sets (streams, pipelines), 1 .. 8 */
+    int32_t copy_streams;         /* host -> device upload streams, 1 .. 8; frames go to
+                                     them in turn (several copy engines at once) */
 } lbpf_server_cfg;
 
 /* One frame to serve. t_arrival: seconds on the server clock

@@ -6,7 +6,8 @@
 //
 // Threads: the caller's thread(s) submit and poll; the server thread owns
 // the schedule (release at arrival time, admission by slots and byte
-// budget, uploads, batch formation, completion) and is the only thread that
+// budget, uploads spread over several copy streams, batch formation,
+// completion) and is the only thread that
 // issues HIP work on the server's streams. The two sides meet in `pending`
 // (submitted requests) and `done` (finished ones), both under `mu`.
 #include <hip/hip_runtime.h>
@@ -36,6 +37,7 @@ constexpr int32_t kMaxBoxesPerFrame = 64;
 constexpr int32_t kMaxSlots = 4096;
 constexpr int32_t kMaxSide = 4096;
 constexpr int32_t kMaxInflight = 8;
+constexpr int32_t kMaxCopyStreams = 8;
 
 struct Req {
     int64_t id = 0;
@@ -43,7 +45,9 @@ struct Req {
     const uint8_t *grey = nullptr;
     const uint16_t *depth = nullptr;
     std::vector<int32_t> boxes;  // [n][4] x, y, w, h
+    int32_t y0 = 0, y1 = 0;      // rows the boxes span (only these are uploaded)
     int32_t slot = -1;
+    int32_t cs = 0;    // copy stream of its upload
     uint64_t seq = 0;  // upload order
 };
 
@@ -81,7 +85,7 @@ struct lbpf_server {
     uint8_t *d_grey = nullptr;
     uint16_t *d_depth = nullptr;
     std::vector<lbpf_image> images;  // one per slot
-    hipStream_t copy_stream = nullptr;
+    std::vector<hipStream_t> copy_streams;
     std::vector<hipEvent_t> slot_ev;  // end of the copies into each slot
     std::vector<Set> sets;
     Clock::time_point t0;
@@ -145,13 +149,22 @@ bool admit(lbpf_server *S, bool &worked) {
         r.slot = S->free_slots.front();
         S->free_slots.pop_front();
         S->bytes_in_use += (int64_t)S->frame_bytes;
-        const size_t o = (size_t)r.slot * S->plane_px;
-        hipError_t e = hipMemcpyAsync(S->d_grey + o, r.grey, S->plane_px, hipMemcpyHostToDevice,
-                                      S->copy_stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(S->d_depth + o, r.depth, 2 * S->plane_px, hipMemcpyHostToDevice,
-                               S->copy_stream);
-        if (e == hipSuccess) e = hipEventRecord(S->slot_ev[(size_t)r.slot], S->copy_stream);
+        r.cs = (int32_t)(S->seq % S->copy_streams.size());
+        hipStream_t cs = S->copy_streams[(size_t)r.cs];
+        // Only the rows the frame's boxes span: the kernels read nothing
+        // else of the slot (their reads past a crop's right edge stay inside
+        // the slot's plane and are never used).
+        const size_t o = (size_t)r.slot * S->plane_px + (size_t)r.y0 * (size_t)c.frame_w;
+        const size_t px = (size_t)(r.y1 - r.y0) * (size_t)c.frame_w;
+        const size_t src = (size_t)r.y0 * (size_t)c.frame_w;
+        hipError_t e = hipSuccess;
+        if (px) {
+            e = hipMemcpyAsync(S->d_grey + o, r.grey + src, px, hipMemcpyHostToDevice, cs);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(S->d_depth + o, r.depth + src, 2 * px, hipMemcpyHostToDevice,
+                                   cs);
+        }
+        if (e == hipSuccess) e = hipEventRecord(S->slot_ev[(size_t)r.slot], cs);
         if (e != hipSuccess) {
             thread_fail(S, e, "frame upload");
             return false;
@@ -172,8 +185,9 @@ bool launch(lbpf_server *S, std::vector<lbpf_box> &boxes, bool &worked) {
         Set &st = S->sets[(size_t)si];
         st.batch.clear();
         boxes.clear();
-        int32_t last = -1;
-        uint64_t last_seq = 0;
+        // Per copy stream, the slot of the batch's newest frame uploaded there.
+        int32_t last[kMaxCopyStreams];
+        uint64_t last_seq[kMaxCopyStreams] = {};
         while (!S->admitted.empty() && (int32_t)st.batch.size() < S->cfg.max_batch_frames) {
             Req r = std::move(S->admitted.front());
             S->admitted.pop_front();
@@ -181,19 +195,23 @@ bool launch(lbpf_server *S, std::vector<lbpf_box> &boxes, bool &worked) {
             for (size_t k = 0; k < nb; ++k)
                 boxes.push_back(lbpf_box{r.slot, r.boxes[4 * k], r.boxes[4 * k + 1],
                                          r.boxes[4 * k + 2], r.boxes[4 * k + 3]});
-            if (r.seq > last_seq) {
-                last_seq = r.seq;
-                last = r.slot;
+            if (r.seq > last_seq[r.cs]) {
+                last_seq[r.cs] = r.seq;
+                last[r.cs] = r.slot;
             }
             st.batch.push_back(std::move(r));
         }
-        // Copies run in order on the copy stream: the newest frame's event
-        // covers the whole batch.
-        hipError_t e = hipStreamWaitEvent(st.stream, S->slot_ev[(size_t)last], 0);
-        if (e != hipSuccess) {
-            thread_fail(S, e, "hipStreamWaitEvent");
-            return false;
+        // Copies run in order on each copy stream: per stream, the newest
+        // frame's event covers the batch's other frames uploaded there.
+        for (size_t c = 0; c < S->copy_streams.size(); ++c) {
+            if (!last_seq[c]) continue;
+            const hipError_t e = hipStreamWaitEvent(st.stream, S->slot_ev[(size_t)last[c]], 0);
+            if (e != hipSuccess) {
+                thread_fail(S, e, "hipStreamWaitEvent");
+                return false;
+            }
         }
+        hipError_t e;
         if (lbpf_pipeline_launch(st.pipe, S->images.data(), (int32_t)S->images.size(),
                                  boxes.data(), (int32_t)boxes.size(), st.stream) != LBPF_OK) {
             thread_fail_status(S, "pipeline launch");
@@ -322,9 +340,10 @@ void release(lbpf_server *S) {
         if (st.argmax) (void)hipFree(st.argmax);
         if (st.argmax_host) (void)hipHostFree(st.argmax_host);
     }
-    if (S->copy_stream) {
-        (void)hipStreamSynchronize(S->copy_stream);
-        (void)hipStreamDestroy(S->copy_stream);
+    for (hipStream_t cs : S->copy_streams) {
+        if (!cs) continue;
+        (void)hipStreamSynchronize(cs);
+        (void)hipStreamDestroy(cs);
     }
     for (hipEvent_t ev : S->slot_ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -354,6 +373,8 @@ lbpf_status lbpf_server_create(lbpf_ctx *ctx, const lbpf_weights *weights,
         return set_last_error(LBPF_E_INVALID, "max_boxes_per_frame out of range");
     if (c.inflight < 1 || c.inflight > kMaxInflight)
         return set_last_error(LBPF_E_INVALID, "inflight out of range");
+    if (c.copy_streams < 1 || c.copy_streams > kMaxCopyStreams)
+        return set_last_error(LBPF_E_INVALID, "copy_streams out of range");
     const size_t plane_px = (size_t)c.frame_w * (size_t)c.frame_h;
     if (c.budget_bytes < (int64_t)(3 * plane_px))
         return set_last_error(LBPF_E_INVALID, "budget_bytes cannot hold one frame");
@@ -401,8 +422,10 @@ lbpf_status lbpf_server_create(lbpf_ctx *ctx, const lbpf_weights *weights,
             return hip_bail(e, "hipEventCreate");
         S->free_slots.push_back(i);
     }
-    if ((e = hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking)) != hipSuccess)
-        return hip_bail(e, "hipStreamCreate");
+    S->copy_streams.assign((size_t)c.copy_streams, nullptr);
+    for (hipStream_t &cs : S->copy_streams)
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
+            return hip_bail(e, "hipStreamCreate");
     S->sets.resize((size_t)c.inflight);
     for (int32_t i = 0; i < c.inflight; ++i) {
         Set &st = S->sets[(size_t)i];
@@ -475,6 +498,13 @@ lbpf_status lbpf_server_submit(lbpf_server *S, const lbpf_request *reqs, int32_t
         r.grey = q.grey;
         r.depth = q.depth;
         r.boxes.assign(q.boxes, q.boxes + 4 * (size_t)q.n_boxes);
+        r.y0 = c.frame_h;
+        r.y1 = 0;
+        for (int32_t k = 0; k < q.n_boxes; ++k) {
+            r.y0 = std::min(r.y0, q.boxes[4 * k + 1]);
+            r.y1 = std::max(r.y1, q.boxes[4 * k + 1] + q.boxes[4 * k + 3]);
+        }
+        if (r.y1 <= r.y0) r.y0 = r.y1 = 0;  // no boxes: nothing to upload
     }
     {
         std::lock_guard<std::mutex> lk(S->mu);

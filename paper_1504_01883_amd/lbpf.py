@@ -96,7 +96,7 @@ class ServerCfg(ctypes.Structure):
     _fields_ = [("frame_w", ctypes.c_int32), ("frame_h", ctypes.c_int32),
                 ("n_slots", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
                 ("max_batch_frames", ctypes.c_int32), ("max_boxes_per_frame", ctypes.c_int32),
-                ("inflight", ctypes.c_int32)]
+                ("inflight", ctypes.c_int32), ("copy_streams", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -373,10 +373,10 @@ class Server:
 
     def __init__(self, ctx: "Context", weights: "Weights", frame_w: int, frame_h: int,
                  n_slots: int, budget_bytes: int, max_batch_frames: int,
-                 max_boxes_per_frame: int = 8, inflight: int = 2):
+                 max_boxes_per_frame: int = 8, inflight: int = 2, copy_streams: int = 2):
         self._ctx, self._weights = ctx, weights  # must outlive the server
         cfg = ServerCfg(frame_w, frame_h, n_slots, budget_bytes, max_batch_frames,
-                        max_boxes_per_frame, inflight)
+                        max_boxes_per_frame, inflight, copy_streams)
         h = ctypes.c_void_p()
         _check(load().lbpf_server_create(ctx._h, weights._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -636,9 +636,9 @@ class Context:
 
     def server(self, weights: Weights, frame_w: int, frame_h: int, n_slots: int,
                budget_bytes: int, max_batch_frames: int, max_boxes_per_frame: int = 8,
-               inflight: int = 2) -> Server:
+               inflight: int = 2, copy_streams: int = 2) -> Server:
         return Server(self, weights, frame_w, frame_h, n_slots, budget_bytes, max_batch_frames,
-                      max_boxes_per_frame, inflight)
+                      max_boxes_per_frame, inflight, copy_streams)
 
     def weights(self, W: torch.Tensor, b: torch.Tensor, precision="fp32") -> Weights:
         return Weights(self, W, b, precision)

@@ -490,14 +490,15 @@ def quick_latency(ctx, seconds: float = 30.0, warmup: float = 2.0, plain_seconds
 
 def native_run(ctx, weights, arrivals, frames, boxes_of, warmup: float, n_slots: int = 128,
                budget: int = 128 * FRAME_BYTES, max_batch_frames: int = 64, inflight: int = 2,
-               timeout: float = 120.0) -> dict:
+               copy_streams: int = 2, timeout: float = 120.0) -> dict:
     """Serve `arrivals` [(t, stream, key)] with the native loop (lbpf_server):
     every request is submitted up front with its arrival time, and the
     library thread releases, admits, uploads and batches them. frames[key]:
     pinned (grey, depth) tensors, boxes_of[key]: [n, 4]. Latency = the
     server's completion time minus the arrival time, over arrivals at or
     after `warmup`."""
-    srv = ctx.server(weights, 640, 480, n_slots, budget, max_batch_frames, 8, inflight)
+    srv = ctx.server(weights, 640, 480, n_slots, budget, max_batch_frames, 8, inflight,
+                     copy_streams)
     n = len(arrivals)
     t0 = srv.clock() + 0.05
     t_arr = t0 + np.array([a[0] for a in arrivals], np.float64)
@@ -630,7 +631,7 @@ def bench(args) -> dict:
 
     fused_native = native(1.0, secs, warm)
     sweeps["native"] = []
-    for mult in (4.0, 16.0, 32.0, 64.0, 96.0, 128.0, 192.0, 256.0):
+    for mult in (4.0, 16.0, 32.0, 48.0, 64.0, 80.0, 96.0, 128.0, 192.0, 256.0):
         r = native(mult, 4.0, 0.5)
         sweeps["native"].append(r)
         if r.get("p99_ms") is None or r["p99_ms"] > 1000.0 / fps or r["unfinished"]:

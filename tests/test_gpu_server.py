@@ -79,13 +79,14 @@ def eager_reference(ctx, wts, W, b, frames, prec):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_server_matches_eager_path(setup, prec):
-    """24 frames submitted at once into 4 slots (a 4-frame budget), batches of
-    up to 3 frames on 2 sets: every identity equals the eager path's."""
+    """24 frames submitted at once into 4 slots (a 4-frame budget), uploads
+    spread over 4 copy streams, batches of up to 3 frames on 2 sets: every
+    identity equals the eager path's."""
     ctx, frames, pinned, W, b = setup
     wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda(), precision=prec)
     ref = eager_reference(ctx, wts, W, b, frames, prec)
     srv = ctx.server(wts, FW, FH, n_slots=4, budget_bytes=4 * FRAME_BYTES, max_batch_frames=3,
-                     max_boxes_per_frame=8, inflight=2)
+                     max_boxes_per_frame=8, inflight=2, copy_streams=4)
     n = len(frames)
     t = srv.clock()
     srv.submit(np.arange(n), np.full(n, t), pinned, [f[2] for f in frames])
@@ -110,7 +111,8 @@ def test_server_alone_equals_mix(setup):
     independent)."""
     ctx, frames, pinned, W, b = setup
     wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda(), precision="bf16")
-    srv = ctx.server(wts, FW, FH, n_slots=8, budget_bytes=8 * FRAME_BYTES, max_batch_frames=8)
+    srv = ctx.server(wts, FW, FH, n_slots=8, budget_bytes=8 * FRAME_BYTES, max_batch_frames=8,
+                     copy_streams=1)
     n = len(frames)
     alone = {}
     for i in (0, 7, 23):
@@ -161,6 +163,11 @@ def test_server_rejects_bad_requests(setup):
     with pytest.raises(lbpf.LbpfError) as ei:
         ctx.server(wts, FW, FH, n_slots=2, budget_bytes=FRAME_BYTES - 1, max_batch_frames=2)
     assert ei.value.status == lbpf.LBPF_E_INVALID
+    for bad_cfg in ({"copy_streams": 0}, {"copy_streams": 9}, {"inflight": 0}):
+        with pytest.raises(lbpf.LbpfError) as ei:
+            ctx.server(wts, FW, FH, n_slots=2, budget_bytes=2 * FRAME_BYTES, max_batch_frames=2,
+                       **bad_cfg)
+        assert ei.value.status == lbpf.LBPF_E_INVALID
     # Accepted requests far in the future: destroying the server drops them.
     srv.submit([5], [t], pinned[:1], [frames[0][2]])
     assert srv.stats()["frames"] == 0
