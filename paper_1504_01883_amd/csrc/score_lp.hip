@@ -680,6 +680,16 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
         }
     float best[4];
     int32_t barg[4];
+    // Scores of a wave whose identities all lie inside K (K a multiple of 4)
+    // leave through LDS: the MFMA layout gives every store instruction 32 B
+    // of 32 different rows, so each 32-row block is first written to the
+    // wave's own LDS area (rows padded to 68 floats against bank
+    // conflicts), then stored 16 lanes to a row, 256 contiguous bytes each.
+    // The ring is free once every wave has passed this barrier.
+    constexpr int kSRow = kCW + 4;  // padded row of the staging area, floats
+    const bool staged = S && vec4 && kw + kCW <= K;
+    float *stg = reinterpret_cast<float *>(lds) + wave * 32 * kSRow;
+    if (S) __syncthreads();  // uniform: S is a kernel argument
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int32_t n = n0 + wm * 128 + 32 * i + (lane & 31);
@@ -703,7 +713,9 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
                         }
                     }
                 }
-                if (S && n < N) {
+                if (staged) {
+                    *reinterpret_cast<f32x4 *>(stg + (lane & 31) * kSRow + (kg - kw)) = v;
+                } else if (S && n < N) {
                     float *row = S + (size_t)n * K;
                     if (vec4 && kg + 3 < K) {
                         *reinterpret_cast<f32x4 *>(row + kg) = v;
@@ -714,6 +726,22 @@ __global__ __launch_bounds__(64 * kW) void k_score_lp_big(const uint8_t *__restr
                     }
                 }
             }
+        if (staged) {
+            // Row rr of the block: lanes 16 q .. 16 q + 15 store its kCW
+            // scores (kCW / 64 passes of 4 floats per lane).
+            constexpr int kLanesPerRow = 16, kRowsPer = 64 / kLanesPerRow;
+#pragma unroll
+            for (int r0 = 0; r0 < 32; r0 += kRowsPer) {
+                const int rr = r0 + lane / kLanesPerRow;
+                const int32_t nr = n0 + wm * 128 + 32 * i + rr;
+#pragma unroll
+                for (int c0 = 0; c0 < kCW; c0 += 4 * kLanesPerRow) {
+                    const int c = c0 + 4 * (lane % kLanesPerRow);
+                    const f32x4 v = *reinterpret_cast<const f32x4 *>(stg + rr * kSRow + c);
+                    if (nr < N) *reinterpret_cast<f32x4 *>(S + (size_t)nr * K + kw + c) = v;
+                }
+            }
+        }
         const float ob = __shfl_xor(best[i], 32, 64);
         const int32_t oa = __shfl_xor(barg[i], 32, 64);
         if (ob > best[i] || (ob == best[i] && oa < barg[i])) {
