@@ -99,22 +99,6 @@ __device__ __forceinline__ uint8_t to_e4m3_rne_sat(float f) {
     return (uint8_t)(sign | bits);
 }
 
-// The same encoding with integer rounding: for a >= 2^-6 (normal e4m3) the
-// FP32 pattern keeps its exponent and top 3 mantissa bits, rounded to nearest
-// even by adding 0x7FFFF plus the lowest kept bit, then rebiased (FP32
-// exponent bias 127, e4m3 bias 7); below 2^-6 the value is a multiple of
-// 2^-9 rounded to nearest even by one rint (8 lands on 0x08, the smallest
-// normal, as it should).
-__device__ __forceinline__ uint32_t e4m3_bits(float f) {
-    const uint32_t sign = (__float_as_uint(f) >> 24) & 0x80u;
-    const float a = fabsf(f);
-    if (!(a < 448.0f)) return sign | 0x7Eu;  // saturate (NaN too) to 448
-    if (a < 0.015625f) return sign | (uint32_t)rintf(a * 512.0f);
-    const uint32_t u = __float_as_uint(a);
-    const uint32_t r = u + 0x7FFFFu + ((u >> 20) & 1u);
-    return sign | min((r >> 20) - (120u << 3), 0x7Eu);
-}
-
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
@@ -249,8 +233,14 @@ __global__ __launch_bounds__(256) void k_quant_rows_vec(const float *__restrict_
         for (int c = 0; c < kC; ++c) {
             const int q = c * 64 + lane;
             if (q < nq) {
-                const uint32_t w = e4m3_bits(v[c].x * f) | (e4m3_bits(v[c].y * f) << 8) |
-                                   (e4m3_bits(v[c].z * f) << 16) | (e4m3_bits(v[c].w * f) << 24);
+                // The packed hardware conversion (OCP e4m3, round to nearest
+                // even). Over every float below 464 in magnitude it gives the
+                // same bytes as a saturating round-to-nearest-even encoder
+                // (checked exhaustively on gfx950 against an integer one);
+                // the scaled values here stay below 448 + 2^-13.
+                const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[c].x * f, v[c].y * f, 0, false);
+                const uint32_t w =
+                    (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[c].z * f, v[c].w * f, lo, true);
                 *reinterpret_cast<uint32_t *>(o + 4 * q) = w;
             }
         }
