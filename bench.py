@@ -14,7 +14,8 @@ project's autotuner, replayed from a HIP graph; scoring is the FP32 MFMA GEMM
 + argmax. Extra keys: the uniform batch (4096 crops of 128x128, 256
 identities) as `uniform`; the plain unbatched FP32 GPU path as
 `plain_gpu_path`; a serving run (16 RGB-D streams at 30 fps, BF16 scoring
-against 1,024 identities, 2 s warm-up + 30 s) as `latency`; and the CPU
+against 1,024 identities, 2 s warm-up + 30 s, through the Python loop, the
+plain comparator and the native loop) as `latency`; and the CPU
 oracle on the host as `cpu_baseline` (single thread and all of the host's
 CPU share), which also states the line's accuracy against the oracle.
 
@@ -438,7 +439,8 @@ def main():
         latency = serve.quick_latency(ctx, seconds=args.latency_seconds,
                                       warmup=args.latency_warmup, keep_results=True)
         out["latency"] = {k: v for k, v in latency.items() if not k.startswith("_")}
-        print(f"[bench] serving: p99 {latency['fused_bf16'].get('p99_ms')} ms", file=sys.stderr,
+        print(f"[bench] serving: p99 {latency['fused_bf16'].get('p99_ms')} ms (Python loop), "
+              f"{latency['fused_bf16_native'].get('p99_ms')} ms (native loop)", file=sys.stderr,
               flush=True)
 
     out["cpu_baseline"] = None

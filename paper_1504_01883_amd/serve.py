@@ -441,8 +441,10 @@ def quick_latency(ctx, seconds: float = 30.0, warmup: float = 2.0, plain_seconds
                   pool: int = 24, keep_results: bool = False) -> dict:
     """The serving workload for the headline line: 16 streams x 30 fps Poisson
     arrivals, BF16 scores against 1024 identities, `warmup` + `seconds`
-    measured; then the plain unbatched FP32 path on the first `plain_seconds`
-    of the same arrivals. p50/p99 frame latency and crops/s of both. With
+    measured, through the Python loop with pipeline replays; then the plain
+    unbatched FP32 path on the first `plain_seconds` of the same arrivals;
+    then the same arrivals through the native loop. p50/p99 frame latency
+    and crops/s of each. With
     keep_results the fused run's features and scores are returned under
     "_fused_results" (and the FP32 weights under "_weights") for an accuracy
     statement against the FP64 oracle."""
@@ -476,13 +478,29 @@ def quick_latency(ctx, seconds: float = 30.0, warmup: float = 2.0, plain_seconds
             g, z, bx, ids = raw[(s, i % pool)]
             frames[(s, i)] = (be.host_frame(g, z), bx, ids)
         sch = Scheduler(128, 128 * FRAME_BYTES, max_batch_frames=64)
-        measured, wall, reqs = run(be, sch, arrivals, frames, warmup)
+        measured, wall, reqs = run(be, sch, arrivals, frames, warmup, freeze_gc=True)
         summ = summarize(measured, wall)
         out[name] = {k: summ[k] for k in ("frames", "crops", "crops_per_s", "p50_ms", "p99_ms")
                      if k in summ}
         if keep:
             out["_fused_results"] = [r for r in reqs if r.features is not None]
             out["_weights"] = (W, b)
+        if not plain:
+            fused_ids = {r.rid: r.argmax for r in reqs if r.argmax is not None}
+    # The same arrivals through the native loop (lbpf_server): every host step
+    # in the library's thread. Its identities are compared with the Python
+    # loop's, frame by frame (the same kernels: they must be equal).
+    pinned, boxes_of = {}, {}
+    for key, (g, z, bx, _) in raw.items():
+        pinned[key] = (torch.from_numpy(g).pin_memory(),
+                       torch.from_numpy(z.view(np.int16)).pin_memory())
+        boxes_of[key] = np.asarray(bx, np.int32)
+    nat = native_run(ctx, w_bf16, [(t, s, (s, i % pool)) for (t, s, i) in arr], pinned,
+                     boxes_of, warmup, keep_identities=True)
+    ids = nat.pop("_identities")
+    same = [np.array_equal(a, fused_ids[rid]) for rid, a in ids.items() if rid in fused_ids]
+    nat["identities_equal_to_python_loop"] = float(np.mean(same)) if same else None
+    out["fused_bf16_native"] = nat
     w_bf16.close()
     w_fp32.close()
     return out
@@ -490,7 +508,8 @@ def quick_latency(ctx, seconds: float = 30.0, warmup: float = 2.0, plain_seconds
 
 def native_run(ctx, weights, arrivals, frames, boxes_of, warmup: float, n_slots: int = 128,
                budget: int = 128 * FRAME_BYTES, max_batch_frames: int = 64, inflight: int = 2,
-               copy_streams: int = 2, timeout: float = 120.0) -> dict:
+               copy_streams: int = 2, timeout: float = 120.0,
+               keep_identities: bool = False) -> dict:
     """Serve `arrivals` [(t, stream, key)] with the native loop (lbpf_server):
     every request is submitted up front with its arrival time, and the
     library thread releases, admits, uploads and batches them. frames[key]:
@@ -506,13 +525,18 @@ def native_run(ctx, weights, arrivals, frames, boxes_of, warmup: float, n_slots:
     n_box = np.array([len(boxes_of[k]) for k in keys], np.int64)
     srv.submit(np.arange(n), t_arr, [frames[k] for k in keys], [boxes_of[k] for k in keys])
     t_done = np.full(n, np.nan)
+    identities = {}
     got = 0
     deadline = time.monotonic() + (t_arr[-1] - srv.clock() if n else 0.0) + timeout
     while got < n:
-        res, _ = srv.poll(65536)
+        res, amax = srv.poll(65536)
         if len(res):
             t_done[res["id"]] = res["t_done"]
             got += len(res)
+            if keep_identities:
+                for r in res:
+                    o = int(r["argmax_offset"])
+                    identities[int(r["id"])] = amax[o:o + int(r["n_boxes"])].copy()
         elif time.monotonic() > deadline:
             break
         else:
@@ -532,6 +556,8 @@ def native_run(ctx, weights, arrivals, frames, boxes_of, warmup: float, n_slots:
            "server": {"batches": st["batches"], "frames_per_batch": st["frames"] / max(st["batches"], 1),
                       "deferring_iterations": st["deferrals"],
                       "thread_busy_fraction": st["busy_seconds"] / max(st["seconds"], 1e-9)}}
+    if keep_identities:
+        out["_identities"] = identities
     return out
 
 
