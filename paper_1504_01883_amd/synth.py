@@ -156,8 +156,15 @@ def make_ragged(n: int, n_ident: int, workload: int = W_RAGGED, first_sample: in
             for lo in range(0, n, step)]
     if workers > 1 and n > 256:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers) as pool:
+        # close + join, not the context manager's terminate(): the workers
+        # then exit normally instead of being sent SIGTERM (which processes
+        # running under a profiler may not survive cleanly).
+        pool = mp.get_context("fork").Pool(workers)
+        try:
             parts = pool.map(_render_range, jobs)
+        finally:
+            pool.close()
+            pool.join()
     else:
         parts = [_render_range(j) for j in jobs]
     i = 0
