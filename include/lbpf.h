@@ -241,6 +241,29 @@ lbpf_status lbpf_train_ovr(lbpf_ctx *ctx, const float *X, const int32_t *labels,
                            double *b64_opt, int32_t *epochs_opt, void *workspace,
                            size_t workspace_bytes, void *stream);
 
+/* The same training (Sec. 2.5: one max-margin hyperplane per person against
+ * all others) on the Gram matrix, in FP32 throughout: G = X X^T of the
+ * unscaled features on the FP32 matrix cores (the scoring GEMM with X as both
+ * operands), sigma = 1 / (lower median of sqrt(G_ii); 1 if that is 0), then
+ * per class the dual coordinate descent of lbpf_train_ovr (same problem,
+ * same seeded sample order, same stopping rule) with the margins
+ * y_i (sigma^2 sum_j alpha_j y_j G_ij + sum_j alpha_j y_j) kept for every
+ * sample, so that the samples whose projected gradient is zero (which change
+ * nothing) are passed over 64 at a time; W_k = sigma^2 sum_i alpha_ki y_ki x_i
+ * and b_k = sum_i alpha_ki y_ki. Arguments as for lbpf_train_ovr, except:
+ * 1 <= N <= 8192; alpha_io: DEVICE [K][N] FP32 (or NULL; warm != 0 needs it);
+ * workspace: DEVICE, lbpf_train_gram_workspace_bytes(N, K) bytes (the N x N
+ * Gram matrix among them), 16-byte aligned. Results agree with the FP64
+ * trainer to FP32 accuracy, not bit for bit.
+ * Errors: LBPF_E_INVALID, LBPF_E_UNSUPPORTED (D or N above the limits),
+ * LBPF_E_HIP. */
+size_t lbpf_train_gram_workspace_bytes(int32_t N, int32_t K);
+lbpf_status lbpf_train_ovr_gram(lbpf_ctx *ctx, const float *X, const int32_t *labels, int32_t N,
+                                int32_t K, double C, double eps, int32_t max_epochs,
+                                uint64_t seed, float *alpha_io, int32_t warm, float *W, float *b,
+                                int32_t *epochs_opt, void *workspace, size_t workspace_bytes,
+                                void *stream);
+
 /* Nearest-centre tracking (Sec. 2.3, Fig. 4): each face of the previous frame
  * (a track) is followed by the detection of the same stream whose box centre
  * is nearest to its previous centre. prev / cur: HOST int32 [P][4] / [C][4]

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ctx_internal.h"
+#include "gram.h"
 #include "lbpf_internal.h"
 
 using namespace lbpf;
@@ -1043,6 +1044,33 @@ lbpf_status lbpf_train_ovr(lbpf_ctx *ctx, const float *X, const int32_t *labels,
         return fail(LBPF_E_UNSUPPORTED, "training supports D <= 8192 and N <= 12288");
     HIP_TRY(launch_train(X, labels, N, ctx->fp.dim, K, C, eps, max_epochs, seed, alpha_io, warm,
                          W, b, W64_opt, b64_opt, epochs_opt, workspace, (hipStream_t)stream),
+            "training kernel launch");
+    return LBPF_OK;
+}
+
+size_t lbpf_train_gram_workspace_bytes(int32_t N, int32_t K) {
+    return N > 0 && K > 0 ? train_gram_workspace_bytes(N, K) : 0;
+}
+
+lbpf_status lbpf_train_ovr_gram(lbpf_ctx *ctx, const float *X, const int32_t *labels, int32_t N,
+                                int32_t K, double C, double eps, int32_t max_epochs,
+                                uint64_t seed, float *alpha_io, int32_t warm, float *W, float *b,
+                                int32_t *epochs_opt, void *workspace, size_t workspace_bytes,
+                                void *stream) {
+    if (!ctx) return fail(LBPF_E_INVALID, "ctx is NULL");
+    if (!X || !labels || !W || !b || !workspace)
+        return fail(LBPF_E_INVALID, "NULL X, labels, W, b or workspace");
+    if (N < 1 || K < 1) return fail(LBPF_E_INVALID, "N and K must be >= 1");
+    if (!(C > 0.0) || !(eps > 0.0) || max_epochs < 1)
+        return fail(LBPF_E_INVALID, "C and eps must be > 0 and max_epochs >= 1");
+    if (warm && !alpha_io) return fail(LBPF_E_INVALID, "warm start without alpha_io");
+    if ((uintptr_t)workspace & 15u) return fail(LBPF_E_INVALID, "workspace not 16-byte aligned");
+    if (ctx->fp.dim > kTrainMaxD || N > kGramMaxN)
+        return fail(LBPF_E_UNSUPPORTED, "Gram training supports D <= 8192 and N <= 8192");
+    if (workspace_bytes < train_gram_workspace_bytes(N, K))
+        return fail(LBPF_E_INVALID, "workspace smaller than lbpf_train_gram_workspace_bytes(N, K)");
+    HIP_TRY(launch_train_gram(X, labels, N, ctx->fp.dim, K, (float)C, (float)eps, max_epochs, seed,
+                              alpha_io, warm, W, b, epochs_opt, workspace, (hipStream_t)stream),
             "training kernel launch");
     return LBPF_OK;
 }

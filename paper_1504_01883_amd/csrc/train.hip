@@ -26,6 +26,7 @@
 // from the feature matrix (coalesced, one row ahead), scaled in FP64. alpha
 // and the epoch's order live in LDS. One barrier per coordinate step (the
 // dot product's cross-wave sum, double-buffered).
+#include "gram.h"
 #include "lbpf_internal.h"
 
 namespace lbpf {
@@ -235,7 +236,292 @@ hipError_t launch_train_j(const TrainArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// --- Gram form (FP32) ----------------------------------------------------------
+//
+// The same dual coordinate descent, restated on the Gram matrix G = X X^T of
+// the unscaled features (one FP32 matrix-core GEMM). With s2 = sigma^2, the
+// margin of sample i under the current duals is
+//   w.x_i = s2 g_i + c,   g_i = sum_j alpha_j y_j G_ij,   c = sum_j alpha_j y_j
+// (c is the bias feature's share), and a step on alpha_i moves g by
+// (alpha_i' - alpha_i) y_i times row i of G (N values) and c by the same
+// scalar. Most steps change nothing: a sample whose projected gradient is 0
+// leaves alpha and g as they are. The solver wave therefore tests the next
+// 64 samples of the epoch's order at once (one LDS read of g per lane), takes
+// the first whose projected gradient is not 0, updates, and tests again from
+// the sample after it: the same steps as visiting the samples one by one.
+// A second wave draws the next epoch's order meanwhile. FP32 throughout.
+
+constexpr int kGramThreads = 128;  // wave 0 solves, wave 1 draws the next order
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// The zero bias row of the Gram products.
+__global__ __launch_bounds__(256) void k_gram_zero(float *__restrict__ z, int32_t n) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) z[i] = 0.0f;
+}
+
+// Row norms sqrt(G_ii).
+__global__ __launch_bounds__(256) void k_gram_diag(const float *__restrict__ G, int32_t N,
+                                                   float *__restrict__ norms) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < N) norms[i] = sqrtf(G[(size_t)i * N + i]);
+}
+
+// sigma = 1 / (lower median of the norms), 1 when that median is 0: the
+// element of rank (N-1)/2, ties ranked by index.
+__global__ __launch_bounds__(256) void k_gram_sigma(const float *__restrict__ norms, int32_t N,
+                                                    float *__restrict__ sigma) {
+    const uint32_t want = (uint32_t)(N - 1) / 2;
+    for (int32_t i = threadIdx.x; i < N; i += 256) {
+        const float v = norms[i];
+        uint32_t rank = 0;
+        for (int32_t j = 0; j < N; ++j) {
+            const float u = norms[j];
+            rank += (u < v || (u == v && j < i)) ? 1u : 0u;
+        }
+        if (rank == want) *sigma = v > 0.0f ? 1.0f / v : 1.0f;
+    }
+}
+
+// A[k][i] = alpha[k][i] y_ki, the left operand of a warm start's margins.
+__global__ __launch_bounds__(256) void k_gram_alpha_y(const float *__restrict__ alpha,
+                                                      const int32_t *__restrict__ labels,
+                                                      int32_t N, int32_t K, float *__restrict__ A) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)N * K) return;
+    const int32_t k = (int32_t)(e / (size_t)N), i = (int32_t)(e % (size_t)N);
+    A[e] = labels[i] == k ? alpha[e] : -alpha[e];
+}
+
+struct GramArgs {
+    const float *G;          // [N][N]
+    const int32_t *labels;
+    const float *sigma;
+    const float *g0;         // [K][N] margins sum_j alpha_j y_j G_ij of a warm start, or null
+    int32_t N, K;
+    float C, eps;
+    int32_t max_epochs;
+    uint64_t seed;
+    float *alpha;            // [K][N]: warm start in (with g0), final values out
+    float *b;                // [K]
+    int32_t *epochs;         // [K] or null
+};
+
+// Epoch e's order (N entries): Fisher-Yates from the identity, i = N-1 down
+// to 1 swapping i with r mod (i+1), r = draw e(N-1) + (N-1-i) of the class's
+// splitmix64 stream. One wave: the draws of 64 swaps in parallel, then the
+// swaps one after another by lane 0 (each needs the previous one's result).
+__device__ void gram_order(int16_t *ord, int32_t N, uint64_t state0, int32_t e, int lane) {
+    for (int32_t p = lane; p < N; p += 64) ord[p] = (int16_t)p;
+    const uint64_t base = (uint64_t)e * (uint64_t)(N - 1);
+    for (int32_t top = N - 1; top > 0; top -= 64) {
+        const int32_t i = top - lane;
+        int32_t j = 0;
+        if (i > 0) {
+            const uint64_t r = splitmix64_at(state0, base + (uint64_t)(N - 1 - i));
+            j = (int32_t)(r % (uint64_t)(i + 1));
+        }
+        const int cnt = min(64, top);
+        for (int t = 0; t < cnt; ++t) {
+            const int32_t jt = __builtin_amdgcn_readlane(j, t);
+            const int32_t it = top - t;
+            if (lane == 0) {
+                const int16_t u = ord[it], v = ord[jt];
+                ord[it] = v;
+                ord[jt] = u;
+            }
+        }
+    }
+}
+
+// One workgroup of two waves per class. Dynamic LDS (17 N bytes): g, alpha,
+// the diagonal s2 G_ii + 1 (FP32 each), two epoch orders (int16) and y (int8).
+__global__ __launch_bounds__(kGramThreads) void k_train_gram(GramArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int32_t N = a.N;
+    float *g = reinterpret_cast<float *>(smem);
+    float *al = g + N;
+    float *qd = al + N;
+    int16_t *ord = reinterpret_cast<int16_t *>(qd + N);  // [2][N]
+    int8_t *ys = reinterpret_cast<int8_t *>(ord + 2 * N);
+    __shared__ int32_t done[2];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int32_t k = blockIdx.x;
+    const float sig = *a.sigma, s2 = sig * sig, C = a.C;
+    const bool warm = a.g0 != nullptr;
+    for (int32_t i = tid; i < N; i += kGramThreads) {
+        ys[i] = a.labels[i] == k ? 1 : -1;
+        al[i] = warm ? a.alpha[(size_t)k * N + i] : 0.0f;
+        g[i] = warm ? a.g0[(size_t)k * N + i] : 0.0f;
+        qd[i] = s2 * a.G[(size_t)i * N + i] + 1.0f;
+    }
+    const uint64_t state0 = a.seed ^ (0x5851F42D4C957F2Dull * (uint64_t)(k + 1));
+    if (wave == 1) gram_order(ord, N, state0, 0, lane);
+    __syncthreads();
+
+    float c = 0.0f;  // solver wave: sum alpha y (the bias weight)
+    if (wave == 0 && warm) {
+        float part = 0.0f;
+        for (int32_t i = lane; i < N; i += 64) part += ys[i] > 0 ? al[i] : -al[i];
+        c = wave_sum_f32(part);
+    }
+    int32_t epoch = 0;
+    while (epoch < a.max_epochs) {
+        if (wave == 0) {
+            const int16_t *od = ord + (epoch & 1) * N;
+            float max_pg = 0.0f;
+            int32_t s = 0;
+            while (s < N) {  // uniform
+                const int32_t p = s + lane;
+                const bool v = p < N;
+                const int32_t i = v ? od[p] : 0;
+                const float y = ys[i] > 0 ? 1.0f : -1.0f;
+                const float ai = al[i];
+                const float G = y * (s2 * g[i] + c) - 1.0f;
+                float PG = G;
+                if (ai <= 0.0f) PG = G < 0.0f ? G : 0.0f;
+                else if (ai >= C) PG = G > 0.0f ? G : 0.0f;
+                const uint64_t m = __ballot(v && PG != 0.0f);
+                if (m == 0) {
+                    s += 64;
+                    continue;
+                }
+                const int t = __builtin_ctzll(m);
+                const int32_t it = __builtin_amdgcn_readlane(i, t);
+                const float Gt = readlane_f(G, t), at = readlane_f(ai, t), yt = readlane_f(y, t);
+                max_pg = fmaxf(max_pg, fabsf(readlane_f(PG, t)));
+                const float q = qd[it];
+                if (q > 0.0f) {
+                    const float an = fminf(fmaxf(at - Gt / q, 0.0f), C);
+                    if (lane == 0) al[it] = an;
+                    const float d = (an - at) * yt;
+                    if (d != 0.0f) {
+                        const float *row = a.G + (size_t)it * N;
+#pragma unroll 8
+                        for (int32_t j = lane; j < N; j += 64) g[j] += d * row[j];
+                        c += d;
+                    }
+                }
+                s += t + 1;
+            }
+            if (lane == 0) done[epoch & 1] = max_pg < a.eps;
+        } else if (epoch + 1 < a.max_epochs) {
+            gram_order(ord + ((epoch + 1) & 1) * N, N, state0, epoch + 1, lane);
+        }
+        __syncthreads();
+        const bool stop = done[epoch & 1] != 0;
+        ++epoch;
+        if (stop) break;  // uniform
+    }
+    for (int32_t i = tid; i < N; i += kGramThreads) a.alpha[(size_t)k * N + i] = al[i];
+    if (tid == 0) {
+        a.b[k] = c;
+        if (a.epochs) a.epochs[k] = epoch;
+    }
+}
+
+// W_k = s2 sum_i alpha_ki y_ki x_i (samples in index order, zero duals
+// skipped); thread t owns coordinates t + 256 j.
+template <int kJ>
+__global__ __launch_bounds__(256) void k_gram_weights(const float *__restrict__ X,
+                                                      const int32_t *__restrict__ labels,
+                                                      int32_t N, int32_t D,
+                                                      const float *__restrict__ alpha,
+                                                      const float *__restrict__ sigma,
+                                                      float *__restrict__ W) {
+    __shared__ float coef[1024];
+    const int tid = threadIdx.x;
+    const int32_t k = blockIdx.x;
+    float acc[kJ];
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) acc[j] = 0.0f;
+    for (int32_t i0 = 0; i0 < N; i0 += 1024) {
+        const int32_t n = min(1024, N - i0);
+        __syncthreads();
+        for (int32_t t = tid; t < n; t += 256) {
+            const float av = alpha[(size_t)k * N + i0 + t];
+            coef[t] = labels[i0 + t] == k ? av : -av;
+        }
+        __syncthreads();
+        for (int32_t t = 0; t < n; ++t) {
+            const float cf = coef[t];
+            if (cf == 0.0f) continue;  // uniform
+            const float *x = X + (size_t)(i0 + t) * D;
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) {
+                const int d = tid + 256 * j;
+                if (d < D) acc[j] += cf * x[d];
+            }
+        }
+    }
+    const float sg = *sigma, s2 = sg * sg;
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        const int d = tid + 256 * j;
+        if (d < D) W[(size_t)k * D + d] = s2 * acc[j];
+    }
+}
+
 }  // namespace
+
+size_t train_gram_workspace_bytes(int32_t N, int32_t K) {
+    const size_t n = (size_t)N, kn = (size_t)K * N;
+    return sizeof(float) * (n * n + 2 * n + 64 + 3 * kn);
+}
+
+hipError_t launch_train_gram(const float *X, const int32_t *labels, int32_t N, int32_t D,
+                             int32_t K, float C, float eps, int32_t max_epochs, uint64_t seed,
+                             float *alpha, int32_t warm, float *W, float *b, int32_t *epochs,
+                             void *workspace, hipStream_t s) {
+    const size_t n = (size_t)N, kn = (size_t)K * N;
+    float *G = static_cast<float *>(workspace);
+    float *norms = G + n * n;
+    float *zeros = norms + n;
+    float *sigma = zeros + n;
+    float *A = sigma + 64;
+    float *G0 = A + kn;
+    float *al = alpha ? alpha : G0 + kn;
+    const dim3 blk(256), rows((N + 255) / 256);
+    hipLaunchKernelGGL(k_gram_zero, rows, blk, 0, s, zeros, N);
+    hipError_t e = launch_score_f32(X, N, X, zeros, N, D, G, nullptr, s, 1, nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_diag, rows, blk, 0, s, G, N, norms);
+    hipLaunchKernelGGL(k_gram_sigma, dim3(1), blk, 0, s, norms, N, sigma);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const bool w = warm && alpha;
+    if (w) {
+        hipLaunchKernelGGL(k_gram_alpha_y, dim3((unsigned)((kn + 255) / 256)), blk, 0, s, alpha,
+                           labels, N, K, A);
+        if ((e = launch_score_f32(A, K, G, zeros, N, N, G0, nullptr, s, 1, nullptr)) != hipSuccess)
+            return e;
+    }
+    GramArgs a{G, labels, sigma, w ? G0 : nullptr, N, K, C, eps, max_epochs, seed, al, b, epochs};
+    const size_t lds = 17 * n;
+    if ((e = hipFuncSetAttribute((const void *)k_train_gram,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_train_gram, dim3(K), dim3(kGramThreads), lds, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    auto wts = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(K), blk, 0, s, X, labels, N, D, al, sigma, W);
+    };
+    if (D <= 4 * 256) wts(k_gram_weights<4>);
+    else if (D <= 8 * 256) wts(k_gram_weights<8>);
+    else if (D <= 16 * 256) wts(k_gram_weights<16>);
+    else wts(k_gram_weights<32>);
+    return hipGetLastError();
+}
 
 size_t train_workspace_bytes(int32_t N) { return ((size_t)2 * N + 1) * sizeof(double); }
 

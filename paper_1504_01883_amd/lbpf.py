@@ -33,7 +33,8 @@ EXPORTS = [
     "lbpf_debug_codes", "lbpf_status_string", "lbpf_last_error", "lbpf_features_plain",
     "lbpf_score_plain", "lbpf_batch_set_launch", "lbpf_batch_get_launch", "lbpf_tune_batch",
     "lbpf_graph_create", "lbpf_graph_launch", "lbpf_graph_destroy", "lbpf_warp_crop_bytes",
-    "lbpf_features_warped", "lbpf_train_workspace_bytes", "lbpf_train_ovr", "lbpf_track",
+    "lbpf_features_warped", "lbpf_train_workspace_bytes", "lbpf_train_ovr",
+    "lbpf_train_gram_workspace_bytes", "lbpf_train_ovr_gram", "lbpf_track",
     "lbpf_score_noalloc", "lbpf_pipeline_create", "lbpf_pipeline_launch",
     "lbpf_pipeline_max_boxes", "lbpf_pipeline_destroy", "lbpf_server_create",
     "lbpf_server_clock", "lbpf_server_submit", "lbpf_server_poll", "lbpf_server_get_stats",
@@ -166,6 +167,9 @@ def load():
         "lbpf_train_workspace_bytes": (sz, [i32]),
         "lbpf_train_ovr": (st, [vp, vp, vp, i32, i32, ctypes.c_double, ctypes.c_double, i32,
                                 ctypes.c_uint64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lbpf_train_gram_workspace_bytes": (sz, [i32, i32]),
+        "lbpf_train_ovr_gram": (st, [vp, vp, vp, i32, i32, ctypes.c_double, ctypes.c_double, i32,
+                                     ctypes.c_uint64, vp, i32, vp, vp, vp, vp, sz, vp]),
         "lbpf_track": (st, [vp, vp, vp, i32, vp, vp, i32, ctypes.c_int64, vp, vp, vp]),
         "lbpf_score_noalloc": (st, [vp, i32, vp, vp, i32, i32, vp, vp, vp]),
         "lbpf_pipeline_create": (st, [vp, vp, i32, vp, vp, vp, vp, vp]),
@@ -538,19 +542,38 @@ class Context:
         return hist, cnt
 
     def train(self, X: torch.Tensor, labels: torch.Tensor, K: int, C=1.0, eps=1e-6,
-              max_epochs=200, seed=150401883, alpha=None, warm=False, want_f64=False):
+              max_epochs=200, seed=150401883, alpha=None, warm=False, want_f64=False,
+              solver="gram"):
         """One-vs-rest SVM training on the device -> dict with W, b (FP32) and
-        epochs [K]; W64 / b64 with want_f64; alpha (FP64 [K, N]) is updated in
-        place when given (warm=True starts from it)."""
+        epochs [K]. solver="gram" (default): the FP32 Gram-matrix solver
+        (lbpf_train_ovr_gram), alpha FP32 [K, N]; solver="f64": the FP64
+        solver (lbpf_train_ovr), alpha FP64 [K, N], W64 / b64 with want_f64.
+        alpha is updated in place when given (warm=True starts from it)."""
         if X.dim() != 2 or X.dtype != torch.float32 or not X.is_contiguous():
             raise ValueError("X must be a contiguous FP32 [N, D] tensor")
         if X.shape[1] != self.dim:
             raise ValueError(f"X has {X.shape[1]} columns, the context's feature dim is {self.dim}")
+        if solver not in ("gram", "f64"):
+            raise ValueError("solver must be 'gram' or 'f64'")
         N = X.shape[0]
         lab = labels.to(device=X.device, dtype=torch.int32).contiguous()
         dev = X.device
         W = torch.empty((K, self.dim), dtype=torch.float32, device=dev)
         b = torch.empty((K,), dtype=torch.float32, device=dev)
+        if solver == "gram":
+            if want_f64:
+                raise ValueError("want_f64 needs solver='f64'")
+            if alpha is not None and (alpha.dtype != torch.float32 or tuple(alpha.shape) != (K, N)
+                                      or not alpha.is_contiguous()):
+                raise ValueError("alpha must be a contiguous FP32 [K, N] tensor")
+            ep = torch.empty((K,), dtype=torch.int32, device=dev)
+            nbytes = int(load().lbpf_train_gram_workspace_bytes(N, K))
+            ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=dev)
+            _check(load().lbpf_train_ovr_gram(self._h, _dptr(X), _dptr(lab), N, K, float(C),
+                                              float(eps), int(max_epochs), int(seed),
+                                              _dptr(alpha), int(bool(warm)), _dptr(W), _dptr(b),
+                                              _dptr(ep), _dptr(ws), ws.numel(), _stream()))
+            return {"W": W, "b": b, "epochs": ep, "workspace": ws}
         W64 = torch.empty((K, self.dim), dtype=torch.float64, device=dev) if want_f64 else None
         b64 = torch.empty((K,), dtype=torch.float64, device=dev) if want_f64 else None
         ep = torch.empty((K,), dtype=torch.int32, device=dev)
