@@ -29,6 +29,8 @@
 #include "gram.h"
 #include "lbpf_internal.h"
 
+#include <algorithm>
+
 namespace lbpf {
 
 namespace {
@@ -251,8 +253,6 @@ hipError_t launch_train_j(const TrainArgs &a, hipStream_t s) {
 // the sample after it: the same steps as visiting the samples one by one.
 // A second wave draws the next epoch's order meanwhile. FP32 throughout.
 
-constexpr int kGramThreads = 128;  // wave 0 solves, wave 1 draws the next order
-
 __device__ __forceinline__ float wave_sum_f32(float v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_gram_diag(const float *__restrict__ G, 
 __global__ __launch_bounds__(256) void k_gram_sigma(const float *__restrict__ norms, int32_t N,
                                                     float *__restrict__ sigma) {
     const uint32_t want = (uint32_t)(N - 1) / 2;
-    for (int32_t i = threadIdx.x; i < N; i += 256) {
+    for (int32_t i = blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256) {
         const float v = norms[i];
         uint32_t rank = 0;
         for (int32_t j = 0; j < N; ++j) {
@@ -302,6 +302,8 @@ __global__ __launch_bounds__(256) void k_gram_alpha_y(const float *__restrict__ 
     A[e] = labels[i] == k ? alpha[e] : -alpha[e];
 }
 
+constexpr size_t kGramLds = 160 * 1024 - 64;  // dynamic LDS of k_train_gram at most
+
 struct GramArgs {
     const float *G;          // [N][N]
     const int32_t *labels;
@@ -316,21 +318,28 @@ struct GramArgs {
     int32_t *epochs;         // [K] or null
 };
 
-// Epoch e's order (N entries): Fisher-Yates from the identity, i = N-1 down
-// to 1 swapping i with r mod (i+1), r = draw e(N-1) + (N-1-i) of the class's
-// splitmix64 stream. One wave: the draws of 64 swaps in parallel, then the
-// swaps one after another by lane 0 (each needs the previous one's result).
-__device__ void gram_order(int16_t *ord, int32_t N, uint64_t state0, int32_t e, int lane) {
-    for (int32_t p = lane; p < N; p += 64) ord[p] = (int16_t)p;
+// Segment `seg` of `nseg` of epoch e's order (N entries): Fisher-Yates from
+// the identity, i = N-1 down to 1 swapping i with r mod (i+1), r = draw
+// e(N-1) + (N-1-i) of the class's splitmix64 stream; segment s takes the
+// steps i in [max(1, N - (s+1) L), N-1 - s L], L = ceil((N-1) / nseg), and
+// segment 0 first writes the identity. One wave: the draws of 64 swaps in
+// parallel, then the swaps one after another by lane 0 (each needs the
+// previous one's result).
+__device__ void gram_order(int16_t *ord, int32_t N, uint64_t state0, int32_t e, int seg, int nseg,
+                           int lane) {
+    if (seg == 0)
+        for (int32_t p = lane; p < N; p += 64) ord[p] = (int16_t)p;
+    const int32_t L = (N - 1 + nseg - 1) / nseg;
+    const int32_t hi = N - 1 - seg * L, lo = max(1, N - (seg + 1) * L);
     const uint64_t base = (uint64_t)e * (uint64_t)(N - 1);
-    for (int32_t top = N - 1; top > 0; top -= 64) {
+    for (int32_t top = hi; top >= lo; top -= 64) {
         const int32_t i = top - lane;
         int32_t j = 0;
-        if (i > 0) {
+        if (i >= lo) {
             const uint64_t r = splitmix64_at(state0, base + (uint64_t)(N - 1 - i));
             j = (int32_t)(r % (uint64_t)(i + 1));
         }
-        const int cnt = min(64, top);
+        const int cnt = min(64, top - lo + 1);
         for (int t = 0; t < cnt; ++t) {
             const int32_t jt = __builtin_amdgcn_readlane(j, t);
             const int32_t it = top - t;
@@ -343,30 +352,36 @@ __device__ void gram_order(int16_t *ord, int32_t N, uint64_t state0, int32_t e, 
     }
 }
 
-// One workgroup of two waves per class. Dynamic LDS (17 N bytes): g, alpha,
-// the diagonal s2 G_ii + 1 (FP32 each), two epoch orders (int16) and y (int8).
-__global__ __launch_bounds__(kGramThreads) void k_train_gram(GramArgs a) {
+// One workgroup per class: wave 0 solves, waves 1..W draw epoch orders
+// (W = blockDim / 64 - 1). The order of epoch f is built by wave 1 + f mod W
+// in W segments during the W epochs before f, so each wave does 1/W of an
+// order per epoch and every epoch ends at one barrier; W + 1 order buffers
+// (epoch f in buffer f mod (W + 1)). Dynamic LDS ((15 + 2W) N bytes): g,
+// alpha, the diagonal s2 G_ii + 1 (FP32 each), y (int8), the orders (int16).
+// kV4: the Gram rows are read as float4 (N % 4 == 0).
+template <bool kV4>
+__global__ __launch_bounds__(320) void k_train_gram(GramArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int32_t N = a.N;
+    const int W = (int)(blockDim.x >> 6) - 1, B = W + 1;
     float *g = reinterpret_cast<float *>(smem);
     float *al = g + N;
     float *qd = al + N;
-    int16_t *ord = reinterpret_cast<int16_t *>(qd + N);  // [2][N]
-    int8_t *ys = reinterpret_cast<int8_t *>(ord + 2 * N);
+    int16_t *ord = reinterpret_cast<int16_t *>(qd + N);  // [W + 1][N]
+    int8_t *ys = reinterpret_cast<int8_t *>(ord + (size_t)B * N);
     __shared__ int32_t done[2];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int32_t k = blockIdx.x;
     const float sig = *a.sigma, s2 = sig * sig, C = a.C;
     const bool warm = a.g0 != nullptr;
-    for (int32_t i = tid; i < N; i += kGramThreads) {
+    for (int32_t i = tid; i < N; i += (int32_t)blockDim.x) {
         ys[i] = a.labels[i] == k ? 1 : -1;
         al[i] = warm ? a.alpha[(size_t)k * N + i] : 0.0f;
         g[i] = warm ? a.g0[(size_t)k * N + i] : 0.0f;
         qd[i] = s2 * a.G[(size_t)i * N + i] + 1.0f;
     }
     const uint64_t state0 = a.seed ^ (0x5851F42D4C957F2Dull * (uint64_t)(k + 1));
-    if (wave == 1) gram_order(ord, N, state0, 0, lane);
     __syncthreads();
 
     float c = 0.0f;  // solver wave: sum alpha y (the bias weight)
@@ -375,55 +390,90 @@ __global__ __launch_bounds__(kGramThreads) void k_train_gram(GramArgs a) {
         for (int32_t i = lane; i < N; i += 64) part += ys[i] > 0 ? al[i] : -al[i];
         c = wave_sum_f32(part);
     }
-    int32_t epoch = 0;
-    while (epoch < a.max_epochs) {
+    int32_t epoch = a.max_epochs;
+    // e < 0: the first orders only.
+    for (int32_t e = -W; e < a.max_epochs; ++e) {
         if (wave == 0) {
-            const int16_t *od = ord + (epoch & 1) * N;
-            float max_pg = 0.0f;
-            int32_t s = 0;
-            while (s < N) {  // uniform
-                const int32_t p = s + lane;
-                const bool v = p < N;
-                const int32_t i = v ? od[p] : 0;
-                const float y = ys[i] > 0 ? 1.0f : -1.0f;
-                const float ai = al[i];
-                const float G = y * (s2 * g[i] + c) - 1.0f;
-                float PG = G;
-                if (ai <= 0.0f) PG = G < 0.0f ? G : 0.0f;
-                else if (ai >= C) PG = G > 0.0f ? G : 0.0f;
-                const uint64_t m = __ballot(v && PG != 0.0f);
-                if (m == 0) {
-                    s += 64;
-                    continue;
-                }
-                const int t = __builtin_ctzll(m);
-                const int32_t it = __builtin_amdgcn_readlane(i, t);
-                const float Gt = readlane_f(G, t), at = readlane_f(ai, t), yt = readlane_f(y, t);
-                max_pg = fmaxf(max_pg, fabsf(readlane_f(PG, t)));
-                const float q = qd[it];
-                if (q > 0.0f) {
-                    const float an = fminf(fmaxf(at - Gt / q, 0.0f), C);
-                    if (lane == 0) al[it] = an;
-                    const float d = (an - at) * yt;
-                    if (d != 0.0f) {
-                        const float *row = a.G + (size_t)it * N;
-#pragma unroll 8
-                        for (int32_t j = lane; j < N; j += 64) g[j] += d * row[j];
-                        c += d;
+            if (e >= 0) {
+                const int16_t *od = ord + (size_t)(e % B) * N;
+                float max_pg = 0.0f;
+                int32_t s = 0;
+                while (s < N) {  // uniform
+                    const int32_t p = s + lane;
+                    const bool v = p < N;
+                    const int32_t i = v ? od[p] : 0;
+                    const float y = ys[i] > 0 ? 1.0f : -1.0f;
+                    const float ai = al[i], qi = qd[i];
+                    const float G = y * (s2 * g[i] + c) - 1.0f;
+                    float PG = G;
+                    if (ai <= 0.0f) PG = G < 0.0f ? G : 0.0f;
+                    else if (ai >= C) PG = G > 0.0f ? G : 0.0f;
+                    const uint64_t m = __ballot(v && PG != 0.0f);
+                    if (m == 0) {
+                        s += 64;
+                        continue;
                     }
+                    const int t = __builtin_ctzll(m);
+                    const int32_t it = __builtin_amdgcn_readlane(i, t);
+                    const float Gt = readlane_f(G, t), at = readlane_f(ai, t);
+                    const float yt = readlane_f(y, t), q = readlane_f(qi, t);
+                    max_pg = fmaxf(max_pg, fabsf(readlane_f(PG, t)));
+                    if (q > 0.0f) {
+                        const float an = fminf(fmaxf(at - Gt / q, 0.0f), C);
+                        if (lane == 0) al[it] = an;
+                        const float d = (an - at) * yt;
+                        if (d != 0.0f) {
+                            const float *row = a.G + (size_t)it * N;
+                            if constexpr (kV4) {
+                                // 24 float4 per lane in flight (a row of up
+                                // to 6144 values in one round), then the
+                                // updates.
+                                typedef float f4 __attribute__((ext_vector_type(4)));
+                                for (int32_t j0 = 4 * lane; j0 < N; j0 += 256 * 24) {
+                                    f4 r[24];
+#pragma unroll
+                                    for (int u = 0; u < 24; ++u)
+                                        if (j0 + 256 * u < N)
+                                            r[u] = *reinterpret_cast<const f4 *>(row + j0 + 256 * u);
+#pragma unroll
+                                    for (int u = 0; u < 24; ++u) {
+                                        const int32_t j = j0 + 256 * u;
+                                        if (j < N) {
+                                            f4 gv = *reinterpret_cast<const f4 *>(g + j);
+                                            gv.x += d * r[u].x;
+                                            gv.y += d * r[u].y;
+                                            gv.z += d * r[u].z;
+                                            gv.w += d * r[u].w;
+                                            *reinterpret_cast<f4 *>(g + j) = gv;
+                                        }
+                                    }
+                                }
+                            } else {
+#pragma unroll 8
+                                for (int32_t j = lane; j < N; j += 64) g[j] += d * row[j];
+                            }
+                            c += d;
+                        }
+                    }
+                    s += t + 1;
                 }
-                s += t + 1;
+                if (lane == 0) done[e & 1] = max_pg < a.eps;
             }
-            if (lane == 0) done[epoch & 1] = max_pg < a.eps;
-        } else if (epoch + 1 < a.max_epochs) {
-            gram_order(ord + ((epoch + 1) & 1) * N, N, state0, epoch + 1, lane);
+        } else {
+            // The epoch f in [e + 1, e + W] with f = wave - 1 (mod W), at
+            // its segment e - f + W.
+            const int w = wave - 1;
+            const int32_t f = e + 1 + (((w - (e + 1)) % W) + W) % W;
+            if (f >= 0 && f < a.max_epochs)
+                gram_order(ord + (size_t)(f % B) * N, N, state0, f, (int)(e - f + W), W, lane);
         }
         __syncthreads();
-        const bool stop = done[epoch & 1] != 0;
-        ++epoch;
-        if (stop) break;  // uniform
+        if (e >= 0 && done[e & 1] != 0) {  // uniform
+            epoch = e + 1;
+            break;
+        }
     }
-    for (int32_t i = tid; i < N; i += kGramThreads) a.alpha[(size_t)k * N + i] = al[i];
+    for (int32_t i = tid; i < N; i += (int32_t)blockDim.x) a.alpha[(size_t)k * N + i] = al[i];
     if (tid == 0) {
         a.b[k] = c;
         if (a.epochs) a.epochs[k] = epoch;
@@ -496,7 +546,7 @@ hipError_t launch_train_gram(const float *X, const int32_t *labels, int32_t N, i
     hipError_t e = launch_score_f32(X, N, X, zeros, N, D, G, nullptr, s, 1, nullptr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gram_diag, rows, blk, 0, s, G, N, norms);
-    hipLaunchKernelGGL(k_gram_sigma, dim3(1), blk, 0, s, norms, N, sigma);
+    hipLaunchKernelGGL(k_gram_sigma, rows, blk, 0, s, norms, N, sigma);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const bool w = warm && alpha;
     if (w) {
@@ -506,12 +556,19 @@ hipError_t launch_train_gram(const float *X, const int32_t *labels, int32_t N, i
             return e;
     }
     GramArgs a{G, labels, sigma, w ? G0 : nullptr, N, K, C, eps, max_epochs, seed, al, b, epochs};
-    const size_t lds = 17 * n;
-    if ((e = hipFuncSetAttribute((const void *)k_train_gram,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+    // As many order waves (at most 4) as the LDS holds buffers for: (15 + 2W) N
+    // bytes, W >= 1 for every N up to kGramMaxN.
+    const int nw = (int)std::min<size_t>(4, (kGramLds / n - 15) / 2);
+    const size_t lds = (15 + 2 * (size_t)nw) * n;
+    const bool v4 = N % 4 == 0;
+    const void *kern = v4 ? (const void *)k_train_gram<true> : (const void *)k_train_gram<false>;
+    if ((e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
         hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_train_gram, dim3(K), dim3(kGramThreads), lds, s, a);
+    if (v4)
+        hipLaunchKernelGGL(k_train_gram<true>, dim3(K), dim3(64 * (1 + nw)), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_train_gram<false>, dim3(K), dim3(64 * (1 + nw)), lds, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     auto wts = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(K), blk, 0, s, X, labels, N, D, al, sigma, W);
