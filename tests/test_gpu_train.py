@@ -234,3 +234,26 @@ def test_gram_incremental_enrolment(ctx, ref):
     _, a_cold = ref.score_f64(Xt, cold["W"].cpu().numpy(), cold["b"].cpu().numpy(),
                               want_scores=False)
     assert (a_inc == a_cold).mean() >= 0.98
+
+
+def test_gram_training_full_size_matches_oracle(ctx, ref):
+    """The enrolment workload at its full size: 256 identities x 20 crops of
+    128 x 128 (5,120 samples, D = 7,552), C = 1, eps = 1e-6, the 200-epoch
+    cap. All 256 classes train on the device; the oracle trainer recomputes
+    four of them (one-vs-rest classes are independent, so the others are
+    relabelled as the rest) from its own features."""
+    g, z, lab = synth.make_training_set(256, 20, 128, 128, synth.W_UNIFORM)
+    n = len(lab)
+    X, _, _ = ref.features([(g.reshape(n * 128, 128), z.reshape(n * 128, 128))],
+                           synth.stacked_boxes(n, 128, 128), n_threads=16)
+    out = ctx.train(torch.from_numpy(X).cuda(), torch.from_numpy(lab).cuda(), 256, seed=SEED)
+    torch.cuda.synchronize()
+    m = 4
+    lab_s = np.where(lab < m, lab, m).astype(np.int32)
+    W_ref, b_ref, ep_ref = ref.train_ovr_f64(X, lab_s, m, seed=SEED, n_threads=m)
+    W = out["W"].cpu().numpy()[:m].astype(np.float64)
+    b = out["b"].cpu().numpy()[:m].astype(np.float64)
+    scale = np.abs(W_ref).max()
+    assert np.abs(W - W_ref).max() <= 1e-4 * scale
+    assert np.abs(b - b_ref).max() <= 1e-4 * max(scale, np.abs(b_ref).max())
+    assert ep_ref == 200 and out["epochs"].cpu().numpy().tolist() == [200] * 256
