@@ -147,7 +147,8 @@ def _roofline(kernels):
 def _timed_steps(step, steps, warmup):
     """Warm-up, then `steps` timed steps with three events each (before the
     features, between features and scoring, after scoring) on the current
-    stream. Returns (ms per step, features ms, scoring ms)."""
+    stream. Returns (ms per step, features ms, scoring ms, per-step
+    statistics: median and p90 of each step's span and of its two parts)."""
     import torch
     for i in range(warmup):
         step(i, None)
@@ -161,9 +162,13 @@ def _timed_steps(step, steps, warmup):
     end.record()
     torch.cuda.synchronize()
     ms_step = start.elapsed_time(end) / steps
-    feat_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    score_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    return ms_step, feat_ms, score_ms
+    f = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    sc = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    stats = {"reps": steps, "step_ms_median": float(np.median(f + sc)),
+             "step_ms_p90": float(np.percentile(f + sc, 90)),
+             "features_ms_median": float(np.median(f)), "features_ms_p90": float(np.percentile(f, 90)),
+             "score_ms_median": float(np.median(sc)), "score_ms_p90": float(np.percentile(sc, 90))}
+    return ms_step, float(f.mean()), float(sc.mean()), stats
 
 
 # --- the ragged batch (headline) -------------------------------------------
@@ -223,7 +228,7 @@ def run_ragged(args, ctx, host):
         if ev is not None:
             ev[2].record()
 
-    ms_step, feat_ms, score_ms = _timed_steps(step, args.steps, args.warmup)
+    ms_step, feat_ms, score_ms, stats = _timed_steps(step, args.steps, args.warmup)
     feat_bytes = float(3 * (sizes[:, 0] * sizes[:, 1]).sum() + n * D * 4)
     score_flops = 2.0 * n * K * D
     kernels = {"features": _kernel_entry(feat_ms, "hbm", feat_bytes, "ragged", "features"),
@@ -246,7 +251,7 @@ def run_ragged(args, ctx, host):
         if ev is not None:
             ev[2].record()
 
-    ms3, feat3, score3 = _timed_steps(step3, args.steps, args.warmup)
+    ms3, feat3, score3, _ = _timed_steps(step3, args.steps, args.warmup)
     tf3 = score_flops / (score3 * 1e-3) / 1e12
     split = {"value": n / (ms3 * 1e-3), "unit": "crops/s", "ms_per_step": ms3,
              "features_ms": feat3, "score_ms": score3, "effective_tflops": tf3,
@@ -263,7 +268,7 @@ def run_ragged(args, ctx, host):
                       "crops": n, "identities": K, "dim": D, "mean_area": area,
                       "parallelism": "single GPU"},
            "tuned_launch": tuned, "roofline": _roofline(kernels), "kernels": kernels,
-           "split_f16_scoring": split}
+           "step_stats": stats, "split_f16_scoring": split}
     state = {"planes": planes, "boxes": boxes, "wts": wts, "W": W, "b": b, "hist": hist,
              "S": S, "A": A, "S3": S3, "A3": A3, "keep": (dg, dz, batch, graph, wts3)}
     return out, state
@@ -332,7 +337,7 @@ def run_uniform(args, ctx, host):
         if ev is not None:
             ev[2].record()
 
-    ms_step, feat_ms, score_ms = _timed_steps(step, args.steps, args.warmup)
+    ms_step, feat_ms, score_ms, stats = _timed_steps(step, args.steps, args.warmup)
     feat_bytes = N_CROPS * (SIDE * SIDE * 3 + D * 4)   # grey + depth in, FP32 row out
     score_flops = 2.0 * N_CROPS * N_IDENT * D
     kernels = {"features": _kernel_entry(feat_ms, "hbm", feat_bytes, "uniform", "features"),
@@ -342,7 +347,7 @@ def run_uniform(args, ctx, host):
                                   "8x8 grid, 7552-dim uniform-59 features, 256 identities, FP32 "
                                   "scoring + argmax; one fused feature launch + one scoring call",
                       "crops": N_CROPS, "side": SIDE, "identities": N_IDENT, "dim": D},
-           "roofline": _roofline(kernels), "kernels": kernels}
+           "roofline": _roofline(kernels), "kernels": kernels, "step_stats": stats}
     for bt in batches:
         bt.close()
     state = {"W": W, "b": b, "scores": scores, "argmax": argmax, "hist": hists[0],
@@ -417,7 +422,8 @@ def main():
            "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": res["config"], "roofline": res["roofline"], "kernels": res["kernels"],
-           "tuned_launch": res["tuned_launch"], "split_f16_scoring": res["split_f16_scoring"]}
+           "tuned_launch": res["tuned_launch"], "step_stats": res["step_stats"],
+           "split_f16_scoring": res["split_f16_scoring"]}
     if not headline:
         print(json.dumps(out), flush=True)
         ctx.close()
