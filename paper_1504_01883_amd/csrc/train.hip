@@ -259,6 +259,28 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
     return v;
 }
 
+typedef float gf4 __attribute__((ext_vector_type(4)));
+
+// Eight 16-byte pieces of LDS at byte offsets 0, 1024, .., 7168 from addr,
+// waited for in the same block: the eight results land in distinct registers,
+// so the reads go out back to back.
+__device__ __forceinline__ void lds_read8(uint32_t addr, gf4 (&v)[8]) {
+    asm volatile(
+        "ds_read_b128 %0, %8\n\t"
+        "ds_read_b128 %1, %8 offset:1024\n\t"
+        "ds_read_b128 %2, %8 offset:2048\n\t"
+        "ds_read_b128 %3, %8 offset:3072\n\t"
+        "ds_read_b128 %4, %8 offset:4096\n\t"
+        "ds_read_b128 %5, %8 offset:5120\n\t"
+        "ds_read_b128 %6, %8 offset:6144\n\t"
+        "ds_read_b128 %7, %8 offset:7168\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=v"(v[0]), "=v"(v[1]), "=v"(v[2]), "=v"(v[3]), "=v"(v[4]), "=v"(v[5]), "=v"(v[6]),
+          "=v"(v[7])
+        : "v"(addr)
+        : "memory");
+}
+
 __device__ __forceinline__ float readlane_f(float v, int l) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
@@ -435,16 +457,39 @@ __global__ __launch_bounds__(320) void k_train_gram(GramArgs a) {
                                     for (int u = 0; u < 24; ++u)
                                         if (j0 + 256 * u < N)
                                             r[u] = *reinterpret_cast<const f4 *>(row + j0 + 256 * u);
+                                    // Groups of eight pieces that lie inside g
+                                    // for every lane (2048 (q + 1) <= N - j0 +
+                                    // 4 lane): one LDS round trip a group; the
+                                    // rest piece by piece.
+                                    const int32_t nfull = (N - (j0 - 4 * lane)) / 2048;
 #pragma unroll
-                                    for (int u = 0; u < 24; ++u) {
-                                        const int32_t j = j0 + 256 * u;
-                                        if (j < N) {
-                                            f4 gv = *reinterpret_cast<const f4 *>(g + j);
-                                            gv.x += d * r[u].x;
-                                            gv.y += d * r[u].y;
-                                            gv.z += d * r[u].z;
-                                            gv.w += d * r[u].w;
-                                            *reinterpret_cast<f4 *>(g + j) = gv;
+                                    for (int q = 0; q < 3; ++q) {
+                                        if (q < nfull) {  // uniform
+                                            gf4 gv[8];
+                                            lds_read8((uint32_t)(uintptr_t)(g + j0 + 2048 * q), gv);
+#pragma unroll
+                                            for (int u = 0; u < 8; ++u) {
+                                                gf4 v = gv[u];
+                                                const f4 ru = r[8 * q + u];
+                                                v.x += d * ru.x;
+                                                v.y += d * ru.y;
+                                                v.z += d * ru.z;
+                                                v.w += d * ru.w;
+                                                *reinterpret_cast<gf4 *>(g + j0 + 2048 * q + 256 * u) = v;
+                                            }
+                                        } else {
+#pragma unroll
+                                            for (int u = 8 * q; u < 8 * q + 8; ++u) {
+                                                const int32_t j = j0 + 256 * u;
+                                                if (j < N) {
+                                                    f4 gv = *reinterpret_cast<const f4 *>(g + j);
+                                                    gv.x += d * r[u].x;
+                                                    gv.y += d * r[u].y;
+                                                    gv.z += d * r[u].z;
+                                                    gv.w += d * r[u].w;
+                                                    *reinterpret_cast<f4 *>(g + j) = gv;
+                                                }
+                                            }
                                         }
                                     }
                                 }
