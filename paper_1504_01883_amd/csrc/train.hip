@@ -452,11 +452,14 @@ __global__ __launch_bounds__(320) void k_train_gram(GramArgs a) {
                                 // updates.
                                 typedef float f4 __attribute__((ext_vector_type(4)));
                                 for (int32_t j0 = 4 * lane; j0 < N; j0 += 256 * 24) {
+                                    // Every load unconditional, its address kept
+                                    // inside the row (pieces past the end are
+                                    // not used): guarded loads would keep the old
+                                    // values of r alive across updates.
                                     f4 r[24];
 #pragma unroll
                                     for (int u = 0; u < 24; ++u)
-                                        if (j0 + 256 * u < N)
-                                            r[u] = *reinterpret_cast<const f4 *>(row + j0 + 256 * u);
+                                        r[u] = *reinterpret_cast<const f4 *>(row + min(j0 + 256 * u, N - 4));
                                     // Groups of eight pieces that lie inside g
                                     // for every lane (2048 (q + 1) <= N - j0 +
                                     // 4 lane): one LDS round trip a group; the
@@ -478,10 +481,15 @@ __global__ __launch_bounds__(320) void k_train_gram(GramArgs a) {
                                                 *reinterpret_cast<gf4 *>(g + j0 + 2048 * q + 256 * u) = v;
                                             }
                                         } else {
+                                            // Piece u lies inside g for every lane
+                                            // when base + 256 (u + 1) <= N, for none
+                                            // when base + 256 u >= N (uniform tests).
+                                            const int32_t base = j0 - 4 * lane;
 #pragma unroll
                                             for (int u = 8 * q; u < 8 * q + 8; ++u) {
                                                 const int32_t j = j0 + 256 * u;
-                                                if (j < N) {
+                                                if (base + 256 * u >= N) break;
+                                                if (base + 256 * (u + 1) <= N || j < N) {
                                                     f4 gv = *reinterpret_cast<const f4 *>(g + j);
                                                     gv.x += d * r[u].x;
                                                     gv.y += d * r[u].y;
