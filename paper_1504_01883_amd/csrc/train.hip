@@ -263,7 +263,9 @@ typedef float gf4 __attribute__((ext_vector_type(4)));
 
 // Eight 16-byte pieces of LDS at byte offsets 0, 1024, .., 7168 from addr,
 // waited for in the same block: the eight results land in distinct registers,
-// so the reads go out back to back.
+// so the reads go out back to back. The outputs are early-clobber: a read
+// that returns while later ones are still being issued must not land in the
+// address register.
 __device__ __forceinline__ void lds_read8(uint32_t addr, gf4 (&v)[8]) {
     asm volatile(
         "ds_read_b128 %0, %8\n\t"
@@ -275,8 +277,8 @@ __device__ __forceinline__ void lds_read8(uint32_t addr, gf4 (&v)[8]) {
         "ds_read_b128 %6, %8 offset:6144\n\t"
         "ds_read_b128 %7, %8 offset:7168\n\t"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(v[0]), "=v"(v[1]), "=v"(v[2]), "=v"(v[3]), "=v"(v[4]), "=v"(v[5]), "=v"(v[6]),
-          "=v"(v[7])
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]), "=&v"(v[6]),
+          "=&v"(v[7])
         : "v"(addr)
         : "memory");
 }
