@@ -120,6 +120,28 @@ def _traffic(workload: str, kernel: str):
     return t.get("bytes_per_launch")
 
 
+# Wave64 VALU instructions a second over the chip: 1,024 SIMDs at 2.4 GHz, one
+# instruction per 4 cycles each (16 lanes a cycle).
+VALU_ISSUE_PEAK_GINST = 256 * 4 * 2.4 / 4
+
+
+def _valu_issue(ms: float, workload: str, kernel: str):
+    """The kernel's VALU issue rate against the chip's: SQ_INSTS_VALU per launch
+    from profiles/<workload>_<kernel>_valu.json (same source digest rule as the
+    traffic), divided by this run's duration; None without a matching file."""
+    path = os.path.join(PROFILE_DIR, f"{workload}_{kernel}_valu.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_digest") != _source_digest(KERNEL_SOURCES[kernel]):
+        return None
+    gi = t["sq_insts_valu_per_dispatch"] / (ms * 1e-3) / 1e9
+    return {"insts_per_launch": t["sq_insts_valu_per_dispatch"], "achieved": gi,
+            "peak": VALU_ISSUE_PEAK_GINST, "unit": "G wave64 instructions/s",
+            "frac": gi / VALU_ISSUE_PEAK_GINST}
+
+
 def _events(n):
     import torch
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
@@ -130,7 +152,7 @@ def _kernel_entry(ms, bound, work, workload, kernel):
         gbs = work / (ms * 1e-3) / 1e9
         return {"ms": ms, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic(workload, kernel),
-                "algorithmic_bytes": work}
+                "algorithmic_bytes": work, "valu_issue": _valu_issue(ms, workload, kernel)}
     tf = work / (ms * 1e-3) / 1e12
     return {"ms": ms, "bound": "mfma", "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": tf / FP32_MFMA_PEAK_TFLOPS,
