@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_score_f32_split(
     const float *__restrict__ X, int32_t N, const float *__restrict__ W,
     const float *__restrict__ bias, int32_t K, int32_t D, float *__restrict__ S, int32_t splits,
     float *__restrict__ part, const int32_t *__restrict__ n_dev) {
-    // Tile: 128 feature rows x kTK identities (kTK = 128 or 64); wave w owns
+    // Tile: 128 feature rows x kTK identities (kTK = 256, 128 or 64); wave w owns
     // rows 64 (w & 1) .. +64 and identities (kTK / 2) (w >> 1) .. + kTK / 2 as
     // 2 x kJB blocks of 32 x 32.
     constexpr int kSlice = 128, kTM = 128;
@@ -451,13 +451,27 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
                             float *part, const int32_t *n_dev) {
     if (N <= 0 || K <= 0) return hipSuccess;
     const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
+    // Products large enough for a 128 x 256 tile per CU without splitting D:
+    // 256 identities per tile (48 KB stages, two-stage ring, one workgroup of
+    // 434 registers a lane per CU), 4/3 the matrix work per copied byte of the
+    // 128 x 128 tile. On 16384 x 1024 x 7552: 1858 us against 1941-1947.
+    if (aligned && splits == 1 && D % 32 == 0 && K >= 256 &&
+        (size_t)((N + 127) / 128) * (size_t)((K + 255) / 256) >= 256) {
+        const dim3 g((N + 127) / 128, (K + 255) / 256, 1);
+        hipLaunchKernelGGL((k_score_f32_split<2, 256>), g, dim3(256), 0, s, X, N, W, b, K, D, S,
+                           1, part, n_dev);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !argmax) return e;
+        return launch_argmax(S, N, K, argmax, s, n_dev);
+    }
     if (aligned && splits >= 1 && D % (32 * splits) == 0 && (splits == 1 || part)) {
         dim3 g((N + 127) / 128, (K + kSplitTK - 1) / kSplitTK, splits);
-        // At least two tiles per CU (512 on the 256-CU MI355X): a two-stage
-        // ring (64 KB of LDS), so two workgroups share each CU and cover each
-        // other's stage waits. Otherwise (fewer tiles, or D split over
-        // workgroups, one per CU) a four-stage ring. On 16384 x 1024 x 7552:
-        // 1940-1946 us against 1960-1964.
+        // 128 x 128 tiles. At least two tiles per CU (512 on the 256-CU
+        // MI355X): a two-stage ring (64 KB of LDS; the workgroup's 270
+        // registers a lane still leave one workgroup per CU, and a shallower
+        // ring measured faster than four stages: 1940-1946 us against
+        // 1960-1964 on 16384 x 1024 x 7552). Otherwise (fewer tiles, or D
+        // split over workgroups) a four-stage ring.
         if (splits == 1 && (size_t)g.x * g.y >= 512)
             hipLaunchKernelGGL((k_score_f32_split<2, kSplitTK>), g, dim3(256), 0, s, X, N, W, b, K,
                                D, S, splits, part, n_dev);
