@@ -14,6 +14,8 @@
 //     consecutive d exactly once for both operands.
 #include "lbpf_internal.h"
 
+#include <algorithm>
+
 namespace lbpf {
 
 namespace {
@@ -451,12 +453,24 @@ hipError_t launch_score_f32(const float *X, int32_t N, const float *W, const flo
                             float *part, const int32_t *n_dev) {
     if (N <= 0 || K <= 0) return hipSuccess;
     const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
-    // Products large enough for a 128 x 256 tile per CU without splitting D:
+    // Unsplit products whose tiles fill the CUs in fewer rounds as 128 x 256:
     // 256 identities per tile (48 KB stages, two-stage ring, one workgroup of
     // 434 registers a lane per CU), 4/3 the matrix work per copied byte of the
-    // 128 x 128 tile. On 16384 x 1024 x 7552: 1858 us against 1941-1947.
-    if (aligned && splits == 1 && D % 32 == 0 && K >= 256 &&
-        (size_t)((N + 127) / 128) * (size_t)((K + 255) / 256) >= 256) {
+    // 128 x 128 tile. A round of 128 x 256 tiles takes about 1.91 rounds of
+    // 128 x 128 ones (16384 x 1024 x 7552: 1858 us in 2 rounds against
+    // 1941-1947 in 4), so the wide tile is taken when 1.91 r256 < r128 (on
+    // 5120 x 5120 x 7552, 4 wide rounds against 7: 3.8 ms against 3.45).
+    int cus = 256;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        cus = std::max(cus, 1);
+    }
+    const size_t nt = (size_t)((N + 127) / 128);
+    const size_t r128 = (nt * (size_t)((K + 127) / 128) + cus - 1) / cus;
+    const size_t r256 = (nt * (size_t)((K + 255) / 256) + cus - 1) / cus;
+    if (aligned && splits == 1 && D % 32 == 0 && K >= 256 && 191 * r256 < 100 * r128) {
         const dim3 g((N + 127) / 128, (K + 255) / 256, 1);
         hipLaunchKernelGGL((k_score_f32_split<2, 256>), g, dim3(256), 0, s, X, N, W, b, K, D, S,
                            1, part, n_dev);
