@@ -162,7 +162,7 @@ def test_gram_training_matches_oracle(ctx, ref, n_ident, per, eps, max_epochs):
     """The FP32 Gram solver against the FP64 oracle trainer: weights and
     biases within 1e-4 of the largest weight, the same epoch count (40-epoch
     cap at eps = 1e-6, where neither converges). N = 190 is not a multiple of
-    4: Gram rows read one value per lane, no row cache."""
+    4: the solver reads the Gram rows one value per lane."""
     X, lab = _train_set(ref, n_ident, per)
     W_ref, b_ref, ep_ref = ref.train_ovr_f64(X, lab, n_ident, eps=eps, max_epochs=max_epochs,
                                              seed=SEED, n_threads=8)
@@ -171,6 +171,40 @@ def test_gram_training_matches_oracle(ctx, ref, n_ident, per, eps, max_epochs):
     torch.cuda.synchronize()
     W, b = out["W"].cpu().numpy().astype(np.float64), out["b"].cpu().numpy().astype(np.float64)
     scale = np.abs(W_ref).max()
+    assert np.abs(W - W_ref).max() <= 1e-4 * scale
+    assert np.abs(b - b_ref).max() <= 1e-4 * max(scale, np.abs(b_ref).max())
+    assert int(out["epochs"].max()) == ep_ref
+
+
+def _histogram_rows(rng, N, D, labels, n_lab):
+    """Seeded stand-ins for feature rows: non-negative, unit sum (as the
+    normalised histograms are), drawn around one random centre per label."""
+    centres = rng.gamma(0.3, size=(max(n_lab, 1), D))
+    X = centres[labels] + rng.gamma(0.3, size=(N, D))
+    return (X / X.sum(axis=1, keepdims=True)).astype(np.float32)
+
+
+@pytest.mark.parametrize("N,K,n_lab,max_epochs", [(8192, 3, 2, 3), (8191, 5, 4, 3), (1, 2, 1, 200),
+                                                  (6, 3, 2, 200)])
+def test_gram_training_edge_cases(ctx, ref, N, K, n_lab, max_epochs):
+    """The Gram solver at its size limit and at the degenerate ends, against
+    the FP64 oracle trainer: N = 8192 (the largest N its LDS state allows,
+    four-float Gram rows, two order waves), N = 8191 (one value per lane),
+    one sample, six samples; the last class of every case has no positive
+    sample (labels < n_lab < K). Same bar as the other cases: weights and
+    biases within 1e-4 of the largest weight, the same epoch count."""
+    rng = np.random.default_rng(N)
+    lab = rng.integers(0, n_lab, N).astype(np.int32)
+    lab[:n_lab] = np.arange(n_lab)  # every label below n_lab present
+    X = _histogram_rows(rng, N, ctx.dim, lab, n_lab)
+    W_ref, b_ref, ep_ref = ref.train_ovr_f64(X, lab, K, max_epochs=max_epochs, seed=SEED,
+                                             n_threads=8)
+    out = ctx.train(torch.from_numpy(X).cuda(), torch.from_numpy(lab).cuda(), K,
+                    max_epochs=max_epochs, seed=SEED)
+    torch.cuda.synchronize()
+    W, b = out["W"].cpu().numpy().astype(np.float64), out["b"].cpu().numpy().astype(np.float64)
+    scale = np.abs(W_ref).max()
+    assert scale > 0
     assert np.abs(W - W_ref).max() <= 1e-4 * scale
     assert np.abs(b - b_ref).max() <= 1e-4 * max(scale, np.abs(b_ref).max())
     assert int(out["epochs"].max()) == ep_ref
