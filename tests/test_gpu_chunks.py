@@ -5,6 +5,9 @@ the precision workload's scale).
   N = 2 * 16384 + 1 distinct rows every chunk (including a one-row tail) is
   compared row by row with the exact FP64 product of the quantised operands
   at the FP32 accumulation tolerance, and the argmax with the FP64 oracle.
+* FP32 products whose tiles fill the GPU (no split of D): on every such
+  kernel shape the argmax is the first maximum of the scores, with exact
+  ties planted inside a lane's columns, across lanes, wave halves and tiles.
 * FP32 argmax-only scoring (no caller score buffer) runs in passes of
   16 M / K rows through the context's score scratch: with N * K above 16 M
   the argmax of every row equals the argmax of the same call with caller
@@ -134,3 +137,41 @@ def test_fp32_argmax_only_multipass(ctx, ref):
     top2 = np.sort(S64, axis=1)[:, -2:]
     clear = (top2[:, 1] - top2[:, 0]) > 2 * tol.max(axis=1)
     assert np.array_equal(A[sample][clear], A64[clear])
+
+
+@pytest.mark.parametrize("N,K", [(16384, 1024), (16384, 1000), (8197, 1024), (4096, 1000)])
+def test_fp32_unsplit_argmax_first_maximum(ctx, N, K):
+    """Unsplit FP32 products and their argmax: 128 x 256 tiles (16384 x
+    1024, and 16384 x 1000 with a partial last tile), 128 x 128 tiles on the
+    two-stage ring (8197 x 1024, a ragged row tile) and on the four-stage
+    ring (4096 x 1000). Two groups of identities share a weight row and bias
+    each: group A (3,
+    35, 700: one lane's columns j = 0 and 1, another tile) weighs the first
+    half of the features, group B (129, 160, 900: two lanes of the upper half
+    of a tile, another tile) the second half, and every other identity is
+    small, so each row's best score is tied within one group. The scores of
+    a group must be equal bit for bit (the same sums), and the argmax must be
+    the first maximum of the scores: 3 or 129 (lowest index on ties,
+    Sec. 2.5)."""
+    D = ctx.dim
+    gen = torch.Generator(device="cuda").manual_seed(N + K)
+    X = torch.rand((N, D), device="cuda", generator=gen)
+    X /= X.sum(dim=1, keepdim=True)
+    rng = np.random.default_rng(K)
+    W = (0.01 * rng.standard_normal((K, D))).astype(np.float32)
+    b = (0.01 * rng.standard_normal(K)).astype(np.float32)
+    ga, gb = [3, 35, 700], [129, 160, 900]
+    W[ga] = np.concatenate([np.ones(D // 2), np.zeros(D - D // 2)]).astype(np.float32)
+    W[gb] = np.concatenate([np.zeros(D // 2), np.ones(D - D // 2)]).astype(np.float32)
+    b[ga], b[gb] = 0.25, 0.25
+    wts = ctx.weights(torch.from_numpy(W).cuda(), torch.from_numpy(b).cuda())
+    S, A = ctx.score(X, wts)
+    _, A_only = ctx.score(X, wts, want_scores=False)
+    torch.cuda.synchronize()
+    S, A, A_only = S.cpu().numpy(), A.cpu().numpy(), A_only.cpu().numpy()
+    wts.close()
+    for grp in (ga, gb):
+        assert all(np.array_equal(S[:, grp[0]], S[:, k]) for k in grp[1:])
+    assert np.array_equal(A, np.argmax(S, axis=1))
+    assert np.array_equal(A_only, A)
+    assert set(np.unique(A).tolist()) == {3, 129}
