@@ -150,11 +150,27 @@ __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ S, int
     const float *row = S + (size_t)n * K;
     float best = -INFINITY;
     int32_t arg = K;  // larger than any valid index
-    for (int32_t k = lane; k < K; k += 64) {
-        float v = row[k];
-        if (v > best || arg == K) {
-            best = v;
-            arg = k;
+    if ((K & 3) == 0 && ((uintptr_t)S & 15) == 0) {
+        // Four consecutive identities a lane per step (16-byte loads), still
+        // scanned in increasing order within the lane.
+        typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll 4
+        for (int32_t k = 4 * lane; k < K; k += 256) {
+            const f4 v = *reinterpret_cast<const f4 *>(row + k);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (v[e] > best || arg == K) {
+                    best = v[e];
+                    arg = k + e;
+                }
+        }
+    } else {
+        for (int32_t k = lane; k < K; k += 64) {
+            float v = row[k];
+            if (v > best || arg == K) {
+                best = v;
+                arg = k;
+            }
         }
     }
 #pragma unroll

@@ -92,7 +92,9 @@ def test_boxes_in_frame_bitexact(ctx, ref):
 
 
 def test_degenerate_crops(ctx, ref):
-    """All-zero depth, constant planes, a single valid depth pixel, max side."""
+    """All-zero depth, constant planes, a single valid depth pixel, max side
+    (1024 alone and on both sides), the smallest crop (3 x 3: one interior
+    pixel)."""
     crops = []
     crops.append((np.full((20, 30), 9, np.uint8), np.zeros((20, 30), np.uint16)))
     crops.append((np.full((16, 16), 200, np.uint8), np.full((16, 16), 65535, np.uint16)))
@@ -101,6 +103,8 @@ def test_degenerate_crops(ctx, ref):
     crops.append((np.arange(81, dtype=np.uint8).reshape(9, 9), z))
     crops.append(synth.render_crop(1024, 40, synth.W_TINY, 2, 3000))
     crops.append(synth.render_crop(33, 1024, synth.W_TINY, 3, 3001))
+    crops.append(synth.render_crop(1024, 1024, synth.W_TINY, 4, 3002))
+    crops.append(synth.render_crop(3, 3, synth.W_TINY, 5, 3003))
     planes = [lbpf.to_device_planes(g, z) for g, z in crops]
     boxes = [[i, 0, 0, z.shape[1], z.shape[0]] for i, (g, z) in enumerate(crops)]
     hist, cnt = ctx.features(planes, boxes, with_counts=True)
